@@ -1,0 +1,604 @@
+/*
+ * rpdla_oracle.c -- plain, slow FP64 CPU oracle for the ionization-seeded
+ * electron-acceleration Monte Carlo of arXiv 2509.01741 (Hissi, Ngirmang,
+ * Smith, Chowdhury: forward and backward acceleration by a radially
+ * polarized focus seeded by field ionization of neon).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no source, header, table or constant with the
+ * HIP library: every constant below is typed here on its own.
+ *
+ * Everything is SI, scalar, double precision, evaluated directly from the
+ * defining formulas (real trigonometric form of the fields, explicit Gouy
+ * arctangent, explicit powers of 1+zeta^2).  OpenMP only splits independent
+ * atoms / electrons across threads; each one is computed exactly as a serial
+ * loop would.
+ *
+ * Sections of the paper followed (paper = arXiv 2509.01741):
+ *   - focal-volume Monte Carlo sampling ......... Sec. 2.1 "Ionization"
+ *   - radially polarized fields ................. Sec. 2.1 "Acceleration", Eqs. (1)-(2)
+ *                                                  and the phase definition below them
+ *   - tunnelling (semi-classical) ionization .... Sec. 1 and Sec. 2.1 "Ionization"
+ *   - Newton-Lorentz equations .................. Eqs. (7)-(14)
+ *   - kinetic energy and azimuth ................ text after Eq. (14); Sec. 2.2, Fig. 5 text
+ *   - forward / backward classification ......... Sec. 2.2 (Figs. 4, 7-9, 13-16)
+ *
+ * Readings where the paper is silent or garbled are listed next to the code
+ * that takes them.  Parity status of every function: pinned by the CPU tests
+ * (closed forms, invariants, library routines, printed worked values).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------------
+ * Constants (CODATA 2018 exact / recommended values, SI).
+ * ------------------------------------------------------------------------- */
+#define ORC_C        299792458.0            /* speed of light, m/s            */
+#define ORC_QE       1.602176634e-19        /* elementary charge, C           */
+#define ORC_ME       9.1093837015e-31       /* electron mass, kg              */
+#define ORC_EPS0     8.8541878128e-12       /* vacuum permittivity, F/m       */
+#define ORC_MEC2_MEV 0.51099895000          /* electron rest energy, MeV      */
+#define ORC_EA       5.14220674763e11       /* atomic unit of field, V/m      */
+#define ORC_TAUA     2.4188843265857e-17    /* atomic unit of time, s         */
+#define ORC_EH_EV    27.211386245988        /* Hartree energy, eV             */
+#define ORC_PI       3.14159265358979323846
+
+/* Neon ionization potentials Ne^(k-1)+ -> Ne^k+, k = 1..10, in eV (NIST ASD
+ * values; the paper names the charge states but prints no potentials). */
+static const double orc_ne_ip_ev[10] = {
+    21.564540, 40.96297, 63.4233, 97.1900, 126.247,
+    157.934, 207.271, 239.0970, 1195.80784, 1362.19911};
+
+/* field models */
+enum { ORC_RP_O1 = 1, ORC_RP_O3 = 3, ORC_RP_O5 = 5,
+       ORC_PLANE_LP = 10, ORC_UNIFORM_EB = 11 };
+/* integration window */
+enum { ORC_WIN_ARRIVAL = 0, ORC_WIN_LAB = 1 };
+/* histogram angle */
+enum { ORC_ANG_POLAR = 0, ORC_ANG_AZIMUTH = 1 };
+
+typedef struct {
+    double lambda, w0, tau_fwhm; /* m, m, s (intensity FWHM)                */
+    double amp;                  /* Er amplitude of Eq. (1), V/m             */
+    double phi0;                 /* carrier phase                            */
+    int field, window;
+    double t_before, t_after;    /* window bounds, s                         */
+    double dt;                   /* step / panel width, s                    */
+    double ez_scale, er_scale;   /* multipliers on Ez and on Ex, Ey          */
+    double test_E[3], test_B[3]; /* uniform-field test model                 */
+} orc_laser;
+
+typedef struct {
+    int nE, nA;
+    double logE_min_MeV, logE_max_MeV;
+    int angle;
+} orc_hist_spec;
+
+const double* orc_ne_ip_table(void) { return orc_ne_ip_ev; }
+
+void orc_constants(double out[8])
+{
+    out[0] = ORC_C; out[1] = ORC_QE; out[2] = ORC_ME; out[3] = ORC_EPS0;
+    out[4] = ORC_MEC2_MEV; out[5] = ORC_EA; out[6] = ORC_TAUA; out[7] = ORC_EH_EV;
+}
+
+/* ---------------------------------------------------------------------------
+ * Laser set-up.  Amplitude from peak intensity uses the Gaussian-equivalent
+ * field E0 = sqrt(2 I / (eps0 c)) that Sec. 2.1 attaches to every intensity
+ * (5e19 W/cm^2 -> 1.94e13 V/m, 5e21 W/cm^2 -> 1.94e14 V/m); that value is
+ * the E0 of Eq. (1).  From power, the order-1 beam carries
+ * P = pi w0^2 eps0 c A^2 / 8 (flux of E x H integrated over the focal plane).
+ * Defaults: window [-5 tau, +10 tau] around the pulse, dt = T/200, unit
+ * field scales, field order 5.
+ * ------------------------------------------------------------------------- */
+static void orc_laser_defaults(orc_laser* L, double lambda, double w0, double tau)
+{
+    memset(L, 0, sizeof(*L));
+    L->lambda = lambda; L->w0 = w0; L->tau_fwhm = tau;
+    L->phi0 = 0.0;
+    L->field = ORC_RP_O5;
+    L->window = ORC_WIN_ARRIVAL;
+    L->t_before = 5.0 * tau;
+    L->t_after = 10.0 * tau;
+    L->dt = lambda / ORC_C / 200.0;
+    L->ez_scale = 1.0; L->er_scale = 1.0;
+}
+
+void orc_laser_init_intensity(orc_laser* L, double lambda, double w0, double tau, double I_W_cm2)
+{
+    orc_laser_defaults(L, lambda, w0, tau);
+    double I = I_W_cm2 * 1.0e4; /* W/m^2 */
+    L->amp = sqrt(2.0 * I / (ORC_EPS0 * ORC_C));
+}
+
+void orc_laser_init_power(orc_laser* L, double lambda, double w0, double tau, double P_W)
+{
+    orc_laser_defaults(L, lambda, w0, tau);
+    L->amp = sqrt(8.0 * P_W / (ORC_PI * w0 * w0 * ORC_EPS0 * ORC_C));
+}
+
+/* Rayleigh length z_r = k0 r0^2 / 2 (definition under Eq. (2)). */
+double orc_rayleigh(const orc_laser* L)
+{
+    double k = 2.0 * ORC_PI / L->lambda;
+    return 0.5 * k * L->w0 * L->w0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Counter-based random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11).  Ten rounds of two
+ * 64x64->128 multiplies; the key is bumped by the Weyl constants between
+ * rounds.
+ * ------------------------------------------------------------------------- */
+static void orc_mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0, lo0, hi1, lo1;
+        orc_mulhilo64(M0, c0, &hi0, &lo0);
+        orc_mulhilo64(M1, c2, &hi1, &lo1);
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n1 = lo1;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        uint64_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform variate number j of atom `atom` in configuration `cfg`: key
+ * (seed, cfg), counter (atom, j/4, 0, 0), word j%4; the top 53 bits give
+ * u = (m + 1) 2^-53 in (0, 1].  Streams: j = 0,1,2 position; j = k + 2 is
+ * the ionization threshold of charge state k (k = 1..10). */
+double orc_uniform(uint64_t seed, uint32_t cfg, uint64_t atom, int j)
+{
+    uint64_t ctr[4] = {atom, (uint64_t)(j >> 2), 0, 0};
+    uint64_t key[2] = {seed, (uint64_t)cfg};
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    uint64_t m = out[j & 3] >> 11;
+    return ((double)m + 1.0) * (1.0 / 9007199254740992.0);
+}
+
+/* Focal-volume sampling (Sec. 2.1): ions at rest, uniform in a cylinder about
+ * the propagation axis, focus at the origin: r = R sqrt(u0),
+ * azimuth 2 pi u1, z = zh (2 u2 - 1). */
+void orc_sample_atoms(uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n,
+                      double r_max, double z_half, double* x, double* y, double* z)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t a = first_atom + (uint64_t)i;
+        double u0 = orc_uniform(seed, cfg, a, 0);
+        double u1 = orc_uniform(seed, cfg, a, 1);
+        double u2 = orc_uniform(seed, cfg, a, 2);
+        double r = r_max * sqrt(u0);
+        double th = 2.0 * ORC_PI * u1;
+        x[i] = r * cos(th);
+        y[i] = r * sin(th);
+        z[i] = z_half * (2.0 * u2 - 1.0);
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Fields.
+ *
+ * Radially polarized TM01 focus, Eqs. (1)-(2) with the phase, f^2 and z_r
+ * defined beneath them, B_theta from Maxwell's equations and the w0/z_r
+ * (non-paraxial) corrections the text names.  Derivation: vector potential
+ * A = z^ A0 psi(rho, zeta) exp(i(omega t - k z)) in Lorenz gauge with the
+ * Lax series psi = psi0 + eps^2 psi2 + eps^4 psi4, eps = w0/z_r,
+ * rho = r/w0, zeta = z/z_r.  Writing
+ *     D = 1 + zeta^2,   Psi = phi0 + omega t - k z - rho^2 zeta / D,
+ *     g = exp(-rho^2/D - (t - z/c)^2/tau0^2),
+ *     C_n = A g D^(-n/2) cos(Psi + n atan zeta),
+ *     S_n = A g D^(-n/2) sin(Psi + n atan zeta),
+ * the fields are
+ *   Er/r  = (1/w0)[C2 + eps^2(-C3/2 + rho^2 C4 - rho^4 C5/4)
+ *                  + eps^4(-3C4/8 - 3rho^2 C5/8 + 17rho^4 C6/16 - 3rho^6 C7/8 + rho^8 C8/32)]
+ *   Ez    = eps(S2 - rho^2 S3) + eps^3(S3/2 + rho^2 S4/2 - 5rho^4 S5/4 + rho^6 S6/4)
+ *   cBt/r = (1/w0)[C2 + eps^2(C3/2 + rho^2 C4/2 - rho^4 C5/4)
+ *                  + eps^4(3C4/8 + 3rho^2 C5/8 + 3rho^4 C6/16 - rho^6 C7/4 + rho^8 C8/32)]
+ * Order 1 keeps the first term of each line, order 3 adds the eps^2 terms of
+ * Er and Bt and the eps^3 term of Ez, order 5 keeps everything.
+ *
+ * Readings: (i) the envelope exponent is negative (the printed Eqs. (1)-(2)
+ * lost the minus sign); (ii) the printed Eq. (2) is inconsistent with the
+ * printed phase -- with the phase as printed it fails Gauss's law at order
+ * eps; Ez here is Eq. (2) evaluated at -phi, the Maxwell-consistent sign;
+ * (iii) tau0 = tau_FWHM / sqrt(2 ln 2), so exp(-2 (t-z/c)^2/tau0^2), the
+ * intensity envelope, has full width tau_FWHM at half maximum; (iv) A, the
+ * amplitude of Eq. (1), is held fixed when the order changes.  Order-1 Er is
+ * Eq. (1) exactly (with E0 = A and the paper's phi = -(Psi + 2 atan zeta)).
+ *
+ * Test models: a linearly polarized plane wave Ex = A env cos(omega t - k z
+ * + phi0), By = Ex/c, and uniform static E and B.
+ * ------------------------------------------------------------------------- */
+void orc_field(const orc_laser* L, double x, double y, double z, double t,
+               double E[3], double B[3])
+{
+    const double k = 2.0 * ORC_PI / L->lambda;
+    const double om = ORC_C * k;
+    const double tau0 = L->tau_fwhm / sqrt(2.0 * log(2.0));
+    if (L->field == ORC_UNIFORM_EB) {
+        for (int i = 0; i < 3; ++i) { E[i] = L->test_E[i]; B[i] = L->test_B[i]; }
+        return;
+    }
+    if (L->field == ORC_PLANE_LP) {
+        double s = (t - z / ORC_C) / tau0;
+        double ex = L->amp * exp(-s * s) * cos(om * t - k * z + L->phi0);
+        E[0] = ex; E[1] = 0.0; E[2] = 0.0;
+        B[0] = 0.0; B[1] = ex / ORC_C; B[2] = 0.0;
+        return;
+    }
+    const int order = L->field;
+    const double w0 = L->w0;
+    const double zr = 0.5 * k * w0 * w0;
+    const double eps = w0 / zr;
+    const double rho2 = (x * x + y * y) / (w0 * w0);
+    const double zeta = z / zr;
+    const double D = 1.0 + zeta * zeta;
+    const double Psi = L->phi0 + om * t - k * z - rho2 * zeta / D;
+    const double s = (t - z / ORC_C) / tau0;
+    const double g = exp(-rho2 / D - s * s);
+    const double gouy = atan(zeta);
+    double C[9], S[9];
+    for (int n = 2; n <= 8; ++n) {
+        double a = L->amp * g * pow(D, -0.5 * n);
+        C[n] = a * cos(Psi + n * gouy);
+        S[n] = a * sin(Psi + n * gouy);
+    }
+    const double r2 = rho2, r4 = rho2 * rho2, r6 = r4 * rho2, r8 = r4 * r4;
+    const double e2 = eps * eps, e3 = e2 * eps, e4 = e2 * e2;
+    double PE = C[2];
+    double PB = C[2];
+    double Ez = eps * (S[2] - r2 * S[3]);
+    if (order >= 3) {
+        PE += e2 * (-C[3] / 2.0 + r2 * C[4] - r4 * C[5] / 4.0);
+        PB += e2 * (C[3] / 2.0 + r2 * C[4] / 2.0 - r4 * C[5] / 4.0);
+        Ez += e3 * (S[3] / 2.0 + r2 * S[4] / 2.0 - 5.0 * r4 * S[5] / 4.0 + r6 * S[6] / 4.0);
+    }
+    if (order >= 5) {
+        PE += e4 * (-3.0 * C[4] / 8.0 - 3.0 * r2 * C[5] / 8.0 + 17.0 * r4 * C[6] / 16.0
+                    - 3.0 * r6 * C[7] / 8.0 + r8 * C[8] / 32.0);
+        PB += e4 * (3.0 * C[4] / 8.0 + 3.0 * r2 * C[5] / 8.0 + 3.0 * r4 * C[6] / 16.0
+                    - r6 * C[7] / 4.0 + r8 * C[8] / 32.0);
+    }
+    /* Cartesian projection: Ex = Er x/r, Ey = Er y/r; Bx = -Bt y/r,
+     * By = Bt x/r, Bz = 0 (text before Eq. (8)). */
+    E[0] = L->er_scale * PE * x / w0;
+    E[1] = L->er_scale * PE * y / w0;
+    E[2] = L->ez_scale * Ez;
+    B[0] = -PB * y / (w0 * ORC_C);
+    B[1] = PB * x / (w0 * ORC_C);
+    B[2] = 0.0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Tunnelling rate.  The paper cites the semi-classical (PPT) tunnelling model
+ * without printing a formula; the rate used is the static ADK rate with
+ * l = m = 0 and l* = n* - 1, in atomic units
+ *   w = C^2 Ip (2 F0/F)^(2 n* - 1) exp(-2 F0 / (3 F)),
+ *   n* = Z / sqrt(2 Ip), F0 = (2 Ip)^(3/2), C^2 = 2^(2 n*) / (n* Gamma(2 n*)),
+ * Z the charge after ionization, evaluated in log space.  The rate is set to
+ * exactly zero when F = 0 or ln(w [1/s]) < -700.
+ * ------------------------------------------------------------------------- */
+double orc_adk_lnrate_general(double Ip_au, double Z, double F_au)
+{
+    double nstar = Z / sqrt(2.0 * Ip_au);
+    double F0 = pow(2.0 * Ip_au, 1.5);
+    double lnC2 = 2.0 * nstar * log(2.0) - log(nstar) - lgamma(2.0 * nstar);
+    return lnC2 + log(Ip_au / ORC_TAUA) + (2.0 * nstar - 1.0) * log(2.0 * F0 / F_au)
+           - 2.0 * F0 / (3.0 * F_au);
+}
+
+/* ln of the rate [1/s] of Ne^(k-1)+ -> Ne^k+ at field magnitude Emag [V/m]. */
+double orc_adk_lnrate(int k, double Emag)
+{
+    double Ip = orc_ne_ip_ev[k - 1] / ORC_EH_EV;
+    return orc_adk_lnrate_general(Ip, (double)k, Emag / ORC_EA);
+}
+
+double orc_adk_rate(int k, double Emag)
+{
+    if (!(Emag > 0.0)) return 0.0;
+    double l = orc_adk_lnrate(k, Emag);
+    if (l < -700.0) return 0.0;
+    return exp(l);
+}
+
+static double orc_emag(const orc_laser* L, double x, double y, double z, double t)
+{
+    double E[3], B[3];
+    orc_field(L, x, y, z, t, E, B);
+    return sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+}
+
+/* 4-point Gauss-Legendre nodes / weights on [-1, 1], closed form. */
+static void orc_gl4(double xn[4], double wn[4])
+{
+    double a = sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(6.0 / 5.0));
+    double b = sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(6.0 / 5.0));
+    double wa = (18.0 + sqrt(30.0)) / 36.0;
+    double wb = (18.0 - sqrt(30.0)) / 36.0;
+    xn[0] = -b; xn[1] = -a; xn[2] = a; xn[3] = b;
+    wn[0] = wb; wn[1] = wa; wn[2] = wa; wn[3] = wb;
+}
+
+void orc_gl4_table(double xn[4], double wn[4]) { orc_gl4(xn, wn); }
+
+/* GL-4 estimate of the integral of w_k(|E(x,t)|) dt over [a, b]. */
+static double orc_rate_integral(const orc_laser* L, int k, double x, double y, double z,
+                                double a, double b)
+{
+    double xn[4], wn[4];
+    orc_gl4(xn, wn);
+    double h = 0.5 * (b - a), m = 0.5 * (a + b);
+    double s = 0.0;
+    for (int i = 0; i < 4; ++i)
+        s += wn[i] * orc_adk_rate(k, orc_emag(L, x, y, z, m + h * xn[i]));
+    return h * s;
+}
+
+/* Window of an atom at axial position z (reading: the bounds -5 tau, +10 tau
+ * are taken relative to the pulse peak's arrival at the atom, z/c, so that
+ * every atom sees the whole pulse; the lab-frame window is the alternative). */
+static void orc_window(const orc_laser* L, double z, double* ts, double* te)
+{
+    double tz = (L->window == ORC_WIN_ARRIVAL) ? z / ORC_C : 0.0;
+    *ts = tz - L->t_before;
+    *te = tz + L->t_after;
+}
+
+/* Solve G(t) = target on [lo, hi], G(t) = GL-4 integral of w over [lo, t],
+ * G(lo) = 0 < target <= G(hi): Newton steps with derivative w(t), kept inside
+ * the bracket by bisection.  Start from linear interpolation on the panel;
+ * accept t - d as soon as a Newton correction d is at most
+ * 2^-40 max(|t|, T), or stop when a bisection step is that small. */
+static double orc_solve_crossing(const orc_laser* L, int k, double x, double y, double z,
+                                 double lo, double hi, double target, double Ghi)
+{
+    if (!(target > 0.0)) return lo;
+    const double T = L->lambda / ORC_C;
+    double tl = lo, th = hi;
+    double t = lo + (hi - lo) * (target / Ghi);
+    if (!(t > tl && t < th)) t = 0.5 * (tl + th);
+    for (int it = 0; it < 100; ++it) {
+        double gdiff = orc_rate_integral(L, k, x, y, z, lo, t) - target;
+        if (gdiff == 0.0) return t;
+        if (gdiff > 0.0) th = t; else tl = t;
+        const double tol = ldexp(fmax(fabs(t), T), -40);
+        double w = orc_adk_rate(k, orc_emag(L, x, y, z, t));
+        double tn = NAN;
+        if (w > 0.0) {
+            double d = gdiff / w;
+            if (fabs(d) <= tol) return t - d;   /* converged Newton step */
+            tn = t - d;
+        }
+        if (!(tn > tl && tn < th)) tn = 0.5 * (tl + th);
+        double step = fabs(tn - t);
+        t = tn;
+        if (step <= tol) break;                 /* bracket below tolerance */
+    }
+    return t;
+}
+
+/* Ionization times of one atom.  Sequential charge states k_first..k_last
+ * (text of Sec. 2.1: outer electrons first, then inner).  State k is born
+ * when the accumulated rate since the previous birth reaches an Exp(1)
+ * threshold -ln u (inverse-survival sampling: P(t_k > t) = exp(-int w dt)).
+ * Integrals use GL-4 on panels of width dt laid from the window start; a
+ * state that starts inside a panel integrates the remainder of that panel.
+ * +INF marks a state not reached inside the window (and every later state). */
+void orc_ionize_one(const orc_laser* L, uint64_t seed, uint32_t cfg, uint64_t atom,
+                    double x, double y, double z, int k_first, int k_last, double* tb)
+{
+    const int K = k_last - k_first + 1;
+    for (int s = 0; s < K; ++s) tb[s] = INFINITY;
+    double ts, te;
+    orc_window(L, z, &ts, &te);
+    const double h = L->dt;
+    const int64_t M = (int64_t)ceil((te - ts) / h);
+    int s = 0;
+    double target = -log(orc_uniform(seed, cfg, atom, k_first + 2));
+    double I = 0.0;
+    double tstart = ts;
+    for (int64_t j = 0; j < M && s < K; ++j) {
+        double a = ts + (double)j * h;
+        double b = (j == M - 1) ? te : ts + (double)(j + 1) * h;
+        while (s < K) {
+            double lo = (tstart > a) ? tstart : a;
+            double seg = orc_rate_integral(L, k_first + s, x, y, z, lo, b);
+            if (I + seg < target) { I += seg; break; }
+            double t = orc_solve_crossing(L, k_first + s, x, y, z, lo, b, target - I, seg);
+            tb[s] = t;
+            ++s;
+            if (s < K) {
+                target = -log(orc_uniform(seed, cfg, atom, k_first + s + 2));
+                I = 0.0;
+                tstart = t;
+            }
+        }
+    }
+}
+
+void orc_ionize(const orc_laser* L, uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n,
+                const double* x, const double* y, const double* z, int k_first, int k_last,
+                double* t_birth)
+{
+    const int K = k_last - k_first + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n; ++i)
+        orc_ionize_one(L, seed, cfg, first_atom + (uint64_t)i, x[i], y[i], z[i],
+                       k_first, k_last, t_birth + i * K);
+}
+
+/* ---------------------------------------------------------------------------
+ * Newton-Lorentz push (Eqs. (7)-(14), radiation reaction dropped as the
+ * paper does below 5e22 W/cm^2).  State (x, u) with u = p/(m c):
+ *   dx/dt = c u / gamma,  du/dt = -(e/(m c)) (E + (c u/gamma) x B),
+ *   gamma = sqrt(1 + u.u).
+ * Classical fourth-order Runge-Kutta with fixed step h (reading: the paper's
+ * controlled-step fifth-order scheme is its own integrator; a fixed step
+ * makes the discretized result unique).  Step n starts at t0 + n h; the
+ * last step ends exactly at t_end.
+ * ------------------------------------------------------------------------- */
+static void orc_rhs(const orc_laser* L, double t, const double Y[6], double dY[6])
+{
+    double E[3], B[3];
+    orc_field(L, Y[0], Y[1], Y[2], t, E, B);
+    double gam = sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
+    double vx = ORC_C * Y[3] / gam, vy = ORC_C * Y[4] / gam, vz = ORC_C * Y[5] / gam;
+    const double q = -ORC_QE / (ORC_ME * ORC_C);
+    dY[0] = vx; dY[1] = vy; dY[2] = vz;
+    dY[3] = q * (E[0] + (vy * B[2] - vz * B[1]));
+    dY[4] = q * (E[1] + (vz * B[0] - vx * B[2]));
+    dY[5] = q * (E[2] + (vx * B[1] - vy * B[0]));
+}
+
+void orc_push_one(const orc_laser* L, double t0, double t_end, double h,
+                  const double x0[3], const double u0[3], double xf[3], double uf[3])
+{
+    double Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
+    const int64_t N = (int64_t)ceil((t_end - t0) / h);
+    for (int64_t n = 0; n < N; ++n) {
+        double ta = t0 + (double)n * h;
+        double hn = (n == N - 1) ? t_end - ta : h;
+        double k1[6], k2[6], k3[6], k4[6], Yt[6];
+        orc_rhs(L, ta, Y, k1);
+        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];
+        orc_rhs(L, ta + 0.5 * hn, Yt, k2);
+        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k2[i];
+        orc_rhs(L, ta + 0.5 * hn, Yt, k3);
+        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + hn * k3[i];
+        orc_rhs(L, ta + hn, Yt, k4);
+        for (int i = 0; i < 6; ++i)
+            Y[i] += hn / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    }
+    for (int i = 0; i < 3; ++i) { xf[i] = Y[i]; uf[i] = Y[3 + i]; }
+}
+
+/* Push every born slot from rest (Sec. 2.1: electrons born with zero
+ * momentum at their ionization time).  Slot s belongs to atom
+ * s / slots_per_atom.  Unborn slots (t_birth = +INF) get NaN outputs. */
+void orc_push(const orc_laser* L, int64_t n_slots, const double* t_birth,
+              const double* x0, const double* y0, const double* z0, int slots_per_atom,
+              double* ux, double* uy, double* uz, double* xf, double* yf, double* zf)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_slots; ++s) {
+        int64_t a = s / slots_per_atom;
+        double t0 = t_birth[s];
+        if (!(t0 < INFINITY)) {
+            ux[s] = uy[s] = uz[s] = xf[s] = yf[s] = zf[s] = NAN;
+            continue;
+        }
+        double ts, te;
+        orc_window(L, z0[a], &ts, &te);
+        double X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
+        orc_push_one(L, t0, te, L->dt, X0, U0, XF, UF);
+        ux[s] = UF[0]; uy[s] = UF[1]; uz[s] = UF[2];
+        xf[s] = XF[0]; yf[s] = XF[1]; zf[s] = XF[2];
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Outputs.  Kinetic energy (gamma - 1) m c^2 (text after Eq. (14)), written
+ * as m c^2 u^2 / (gamma + 1); polar emission angle atan2(|u_perp|, u_z);
+ * azimuth psi = atan2(u_y, u_x) (Fig. 5 text); forward iff u_z > 0 (the
+ * final propagation direction, Sec. 2.2).
+ * ------------------------------------------------------------------------- */
+void orc_epilogue(int64_t n, const double* ux, const double* uy, const double* uz,
+                  double* K_MeV, double* theta, double* psi, int32_t* fwd)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double u2 = ux[i] * ux[i] + uy[i] * uy[i] + uz[i] * uz[i];
+        double gam = sqrt(1.0 + u2);
+        K_MeV[i] = ORC_MEC2_MEV * u2 / (gam + 1.0);
+        theta[i] = atan2(sqrt(ux[i] * ux[i] + uy[i] * uy[i]), uz[i]);
+        psi[i] = atan2(uy[i], ux[i]);
+        fwd[i] = (uz[i] > 0.0) ? 1 : 0;
+    }
+}
+
+/* Energy-angle histogram counts[dir][iE][iA], dir 0 = forward, 1 = backward;
+ * log10-energy bins over [logE_min, logE_max); angle bins over [0, pi]
+ * (polar) or (-pi, pi] (azimuth), the top edge folded into the last bin.
+ * Tallies: 0 forward, 1 backward, 2 below range, 3 above range, 4 unborn,
+ * 5 NaN.  Counts and tallies accumulate. */
+void orc_histogram(int64_t n, const double* t_birth, const double* ux, const double* uy,
+                   const double* uz, const orc_hist_spec* sp, uint64_t* counts,
+                   uint64_t* tallies)
+{
+    const double width = (sp->logE_max_MeV - sp->logE_min_MeV) / (double)sp->nE;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(t_birth[i] < INFINITY)) { tallies[4] += 1; continue; }
+        if (isnan(ux[i]) || isnan(uy[i]) || isnan(uz[i])) { tallies[5] += 1; continue; }
+        double u2 = ux[i] * ux[i] + uy[i] * uy[i] + uz[i] * uz[i];
+        double gam = sqrt(1.0 + u2);
+        double K = ORC_MEC2_MEV * u2 / (gam + 1.0);
+        int dir = (uz[i] > 0.0) ? 0 : 1;
+        tallies[dir] += 1;
+        double lk = log10(K);
+        double fe = floor((lk - sp->logE_min_MeV) / width);
+        if (!(fe >= 0.0)) { tallies[2] += 1; continue; }
+        if (fe >= (double)sp->nE) { tallies[3] += 1; continue; }
+        double ang, fa;
+        if (sp->angle == ORC_ANG_POLAR) {
+            ang = atan2(sqrt(ux[i] * ux[i] + uy[i] * uy[i]), uz[i]);
+            fa = floor(ang / ORC_PI * (double)sp->nA);
+        } else {
+            ang = atan2(uy[i], ux[i]);
+            fa = floor((ang + ORC_PI) / (2.0 * ORC_PI) * (double)sp->nA);
+        }
+        int ia = (int)fa;
+        if (ia > sp->nA - 1) ia = sp->nA - 1;
+        if (ia < 0) ia = 0;
+        int ie = (int)fe;
+        counts[((int64_t)dir * sp->nE + ie) * sp->nA + ia] += 1;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Batch helpers for the Python test harness.
+ * ------------------------------------------------------------------------- */
+void orc_field_batch(const orc_laser* L, int64_t n, const double* x, const double* y,
+                     const double* z, const double* t, double* E, double* B)
+{
+    for (int64_t i = 0; i < n; ++i) orc_field(L, x[i], y[i], z[i], t[i], E + 3 * i, B + 3 * i);
+}
+
+void orc_uniform_batch(uint64_t seed, uint32_t cfg, int64_t n, const uint64_t* atom,
+                       const int32_t* j, double* u)
+{
+    for (int64_t i = 0; i < n; ++i) u[i] = orc_uniform(seed, cfg, atom[i], j[i]);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_adk_rate_batch(int k, int64_t n, const double* Emag, double* w)
+{
+    for (int64_t i = 0; i < n; ++i) w[i] = orc_adk_rate(k, Emag[i]);
+}

@@ -1,0 +1,244 @@
+"""Pins for the oracle's field model (Sec. 2.1 'Acceleration', Eqs. (1)-(2),
+the phase definition under them, B_theta from Maxwell's equations and the
+w0/z_r corrections).
+
+Independent checks: the amplitudes and the ~18% intensity ratio the paper
+prints, the power closed form, Maxwell's equations in vacuum (finite-difference
+residuals and their scaling with eps = w0/z_r for each truncation order), and
+the on-axis structure the text states.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+C = 299792458.0
+EPS0 = 8.8541878128e-12
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def test_paper_amplitudes(orc):
+    for key in ("E0_at_5e19", "E0_at_5e21"):
+        g = GOLD[key]
+        L = orc.laser_intensity(0.8e-6, 2.5e-6, 30e-15, g["I_W_cm2"])
+        assert abs(L.amp / g["E0_V_m"] - 1) < g["rel_tol"], key
+
+
+def test_paper_chi(orc):
+    g = GOLD["chi_at_5e21"]
+    L = orc.laser_intensity(0.8e-6, 2.5e-6, 30e-15, 5e21)
+    chi = L.amp / g["Ecr_V_m"]
+    assert abs(chi / g["chi"] - 1) < g["rel_tol"]
+
+
+def test_paper_rest_energy(orc):
+    g = GOLD["rest_energy_MeV"]
+    assert abs(orc.constants()["mec2_MeV"] - g["value"]) < g["abs_tol"]
+    K, _, _, _ = orc.epilogue([0.0], [0.0], [np.sqrt(3.0)])  # gamma = 2
+    assert abs(K[0] - orc.constants()["mec2_MeV"]) < 1e-15
+
+
+def test_rp_peak_intensity_fraction(orc):
+    # focal plane, carrier crest: Er = A rho exp(-rho^2); max^2 = 1/(2e)
+    L = orc.laser_intensity(0.8e-6, 2.5e-6, 1.0, 5e19, field=orc.RP_O1)
+    r = np.linspace(0, 3 * L.w0, 300001)
+    E, _ = orc.field(L, r, 0 * r, 0 * r, 0 * r)
+    frac = (np.abs(E[:, 0]).max() / L.amp) ** 2
+    assert abs(frac - 1 / (2 * np.e)) < 1e-9
+    g = GOLD["rp_peak_intensity_fraction"]
+    assert abs(frac - g["value"]) < g["abs_tol"]
+
+
+def test_power_closed_form(orc):
+    # cycle-averaged Poynting flux through the focal plane of the order-1
+    # continuous-wave beam equals pi w0^2 eps0 c A^2 / 8
+    P = 1e15
+    L = orc.laser_power(1.0e-6, 3e-6, 1.0, P, field=orc.RP_O1)
+    T = L.lambda_ / C
+    r = np.linspace(0, 6 * L.w0, 4001)
+    ts = (np.arange(64) + 0.5) / 64 * T
+    S = np.zeros_like(r)
+    for t in ts:
+        E, B = orc.field(L, r, 0 * r, 0 * r, t + 0 * r)
+        S += (E[:, 0] * B[:, 1] - E[:, 1] * B[:, 0]) * (EPS0 * C * C)  # / mu0
+    S /= len(ts)
+    flux = np.trapezoid(S * 2 * np.pi * r, r)
+    assert abs(flux / P - 1) < 1e-6
+
+
+def _maxwell(orc, order, eps, npts=80, seed=1):
+    lam = 1e-6
+    k = 2 * np.pi / lam
+    w0 = 2 / (k * eps)
+    L = orc.laser_intensity(lam, w0, 1.0, 1e20, field=order)  # tau = 1 s: continuous wave
+    A, zr = L.amp, orc.rayleigh(L)
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0, 2, npts)
+    ph = rng.uniform(0, 2 * np.pi, npts)
+    zeta = rng.uniform(-1.5, 1.5, npts)
+    x, y, z = rho * w0 * np.cos(ph), rho * w0 * np.sin(ph), zeta * zr
+    t = rng.uniform(-1, 1, npts) * lam / C + z / C
+    h = 2e-3 / k
+    ht = h / C
+    co = np.array([1, -8, 8, -1]) / 12.0
+    off = np.array([-2, -1, 1, 2])
+    cache = {}
+
+    def F(axis):
+        if axis not in cache:
+            outs = []
+            for o in off:
+                d = [x, y, z, t]
+                d[axis] = d[axis] + o * (ht if axis == 3 else h)
+                outs.append(orc.field(L, *d))
+            cache[axis] = outs
+        return cache[axis]
+
+    def d(axis, comp, which):
+        s = 0
+        for cf, (E, B) in zip(co, F(axis)):
+            s = s + cf * (E if which == "E" else B)[:, comp]
+        return s / (ht if axis == 3 else h)
+
+    divE = d(0, 0, "E") + d(1, 1, "E") + d(2, 2, "E")
+    curlE = np.stack([d(1, 2, "E") - d(2, 1, "E"), d(2, 0, "E") - d(0, 2, "E"),
+                      d(0, 1, "E") - d(1, 0, "E")], 1)
+    dBdt = np.stack([d(3, i, "B") for i in range(3)], 1)
+    curlB = np.stack([d(1, 2, "B") - d(2, 1, "B"), d(2, 0, "B") - d(0, 2, "B"),
+                      d(0, 1, "B") - d(1, 0, "B")], 1)
+    dEdt = np.stack([d(3, i, "E") for i in range(3)], 1)
+    divB = d(0, 0, "B") + d(1, 1, "B") + d(2, 2, "B")
+    n = k * A
+    vals = (np.abs(divE), np.linalg.norm(curlE + dBdt, axis=1),
+            np.linalg.norm(C * curlB - dEdt / C, axis=1), np.abs(C * divB))
+    return np.array([np.percentile(v / n, 90) for v in vals])
+
+
+# expected scaling exponents of the residuals (div E, Faraday, Ampere) with eps
+@pytest.mark.parametrize("order,slopes", [(1, (3, 2, 2)), (3, (5, 4, 4)), (5, (5, 6, 5))])
+def test_maxwell_residual_scaling(orc, order, slopes):
+    r1 = _maxwell(orc, order, 0.04)
+    r2 = _maxwell(orc, order, 0.16)
+    got = np.log(r2[:3] / r1[:3]) / np.log(4.0)
+    assert np.all(np.abs(got - np.array(slopes)) < 0.15), got
+    assert r1[3] < 1e-12 and r2[3] < 1e-12  # div B = 0 exactly (B is a curl)
+
+
+def test_printed_ez_sign_fails_gauss(orc):
+    """Reading (ii): Eq. (2) as printed, with the printed phase, leaves
+    div E of order eps; the oracle's Ez (Eq. (2) at -phi) leaves eps^3."""
+    lam, k = 1e-6, 2 * np.pi / 1e-6
+    res = []
+    for eps in (0.04, 0.08):
+        w0 = 2 / (k * eps)
+        L = orc.laser_intensity(lam, w0, 1.0, 1e20, field=orc.RP_O1)
+        A, zr = L.amp, orc.rayleigh(L)
+        rng = np.random.default_rng(3)
+        n = 60
+        x = rng.uniform(-1.5, 1.5, n) * w0
+        y = rng.uniform(-1.5, 1.5, n) * w0
+        z = rng.uniform(-1, 1, n) * zr
+        t = z / C + rng.uniform(-1, 1, n) * lam / C
+
+        def ez_printed(x, y, z, t):
+            r2 = x * x + y * y
+            f2 = 1 + (z / zr) ** 2
+            phi = k * z - C * k * t - 2 * np.arctan(z / zr) + z * r2 / (zr * w0 * w0 * f2)
+            return (2 * A / (k * w0 * f2)) * ((1 - r2 / (w0 * w0 * f2)) * np.sin(phi)
+                                              - z * r2 / (zr * w0 * w0 * f2) * np.cos(phi)) \
+                * np.exp(-r2 / (w0 * w0 * f2))
+
+        h = 2e-3 / k
+        dEx = (orc.field(L, x + h, y, z, t)[0][:, 0] - orc.field(L, x - h, y, z, t)[0][:, 0]) / (2 * h)
+        dEy = (orc.field(L, x, y + h, z, t)[0][:, 1] - orc.field(L, x, y - h, z, t)[0][:, 1]) / (2 * h)
+        dEz_or = (orc.field(L, x, y, z + h, t)[0][:, 2] - orc.field(L, x, y, z - h, t)[0][:, 2]) / (2 * h)
+        dEz_pr = (ez_printed(x, y, z + h, t) - ez_printed(x, y, z - h, t)) / (2 * h)
+        res.append((np.percentile(np.abs(dEx + dEy + dEz_pr), 90) / (k * A),
+                    np.percentile(np.abs(dEx + dEy + dEz_or), 90) / (k * A)))
+    res = np.array(res)
+    assert res[0, 0] > 0.1 * 0.04          # printed sign: residual ~ eps
+    assert res[0, 1] < 1e-3 * res[0, 0]    # Maxwell-consistent sign
+    assert abs(np.log2(res[1, 0] / res[0, 0]) - 1) < 0.2
+
+
+def test_order1_er_is_printed_eq1(orc):
+    lam, w0, tau = 0.8e-6, 2.5e-6, 30e-15
+    L = orc.laser_intensity(lam, w0, tau, 5e19, field=orc.RP_O1, phi0=0.3)
+    k = 2 * np.pi / lam
+    zr, A = orc.rayleigh(L), L.amp
+    tau0 = tau / np.sqrt(2 * np.log(2))
+    rng = np.random.default_rng(5)
+    n = 200
+    x, y = rng.uniform(-2, 2, n) * w0, rng.uniform(-2, 2, n) * w0
+    z = rng.uniform(-2, 2, n) * zr
+    t = z / C + rng.uniform(-2, 2, n) * tau
+    r = np.hypot(x, y)
+    f2 = 1 + (z / zr) ** 2
+    phi = k * z - C * k * t - 2 * np.arctan(z / zr) + z * r * r / (zr * w0 * w0 * f2)
+    # the paper's phase carries +phi0 while the oracle's Psi carries +phi0 with
+    # the opposite time sign: cos(phi_paper) with phi0 -> -phi0
+    phi -= 0.3
+    er = A * r / (w0 * f2) * np.cos(phi) * np.exp(-r * r / (w0 * w0 * f2)) \
+        * np.exp(-((t - z / C) / tau0) ** 2)
+    E, _ = orc.field(L, x, y, z, t)
+    er_or = np.where(r > 0, (E[:, 0] * x + E[:, 1] * y) / np.where(r > 0, r, 1), 0)
+    assert np.max(np.abs(er_or - er)) < 1e-12 * A
+
+
+def test_axis_and_poynting(orc):
+    L = orc.laser_intensity(0.8e-6, 2.0e-6, 30e-15, 1e21, field=orc.RP_O5)
+    zr, A = orc.rayleigh(L), L.amp
+    z = np.linspace(-2, 2, 41) * zr
+    t = z / C + 0.37e-15
+    E, B = orc.field(L, 0 * z, 0 * z, z, t)
+    assert np.all(E[:, :2] == 0) and np.all(B == 0)     # Er = Bt = 0 on axis
+    assert np.max(np.abs(E[:, 2])) > 0.05 * A            # Ez alone on axis
+    # order 1 in the focal plane on axis: Ez = eps A env sin(omega t + phi0)
+    L1 = orc.laser_intensity(0.8e-6, 2.0e-6, 30e-15, 1e21, field=orc.RP_O1)
+    om = 2 * np.pi * C / L1.lambda_
+    tau0 = L1.tau_fwhm / np.sqrt(2 * np.log(2))
+    ts = np.linspace(-40e-15, 40e-15, 101)
+    E1, _ = orc.field(L1, 0 * ts, 0 * ts, 0 * ts, ts)
+    eps = L1.w0 / orc.rayleigh(L1)
+    ref = eps * A * np.exp(-(ts / tau0) ** 2) * np.sin(om * ts)
+    assert np.max(np.abs(E1[:, 2] - ref)) < 1e-13 * A
+    # forward energy flow (E x B).z > 0 on the focal plane off axis
+    rng = np.random.default_rng(2)
+    x, y = rng.uniform(-2, 2, 500) * L.w0, rng.uniform(-2, 2, 500) * L.w0
+    tt = rng.uniform(-1, 1, 500) * 1e-15
+    E, B = orc.field(L, x, y, 0 * x, tt)
+    Sz = E[:, 0] * B[:, 1] - E[:, 1] * B[:, 0]
+    big = np.hypot(E[:, 0], E[:, 1]) > 1e-3 * A
+    assert np.all(Sz[big] > 0)
+
+
+def test_plane_wave_and_scales(orc):
+    L = orc.laser_intensity(1e-6, 3e-6, 20e-15, 1e20, field=orc.PLANE_LP)
+    rng = np.random.default_rng(0)
+    x, y, z = rng.normal(size=(3, 50)) * 1e-6
+    t = z / C + rng.normal(size=50) * 10e-15
+    E, B = orc.field(L, x, y, z, t)
+    assert np.all(E[:, 1:] == 0) and np.allclose(B[:, 1], E[:, 0] / C, rtol=0, atol=0)
+    L5 = orc.laser_intensity(0.8e-6, 2e-6, 30e-15, 1e21, field=orc.RP_O5)
+    Ls = orc.laser_intensity(0.8e-6, 2e-6, 30e-15, 1e21, field=orc.RP_O5, er_scale=0.25,
+                             ez_scale=0.5)
+    E0, B0 = orc.field(L5, x, y, z, t)
+    E1, B1 = orc.field(Ls, x, y, z, t)
+    assert np.allclose(E1[:, :2], 0.25 * E0[:, :2], rtol=1e-15, atol=0)
+    assert np.allclose(E1[:, 2], 0.5 * E0[:, 2], rtol=1e-15, atol=0)
+    assert np.array_equal(B1, B0)
+
+
+def test_envelope_fwhm(orc):
+    """Reading (iii): tau is the full width at half maximum of the intensity
+    envelope (carrier removed with a quadrature pair phi0 = 0, pi/2)."""
+    L0 = orc.laser_intensity(0.8e-6, 3e-6, 30e-15, 1e20, field=orc.PLANE_LP, phi0=0.0)
+    L1 = orc.laser_intensity(0.8e-6, 3e-6, 30e-15, 1e20, field=orc.PLANE_LP, phi0=np.pi / 2)
+    ts = np.linspace(-40e-15, 40e-15, 32001)
+    I = orc.field(L0, 0 * ts, 0 * ts, 0 * ts, ts)[0][:, 0] ** 2 \
+        + orc.field(L1, 0 * ts, 0 * ts, 0 * ts, ts)[0][:, 0] ** 2
+    I /= I.max()
+    above = ts[I >= 0.5]
+    fwhm = above[-1] - above[0]
+    assert abs(fwhm - L0.tau_fwhm) < 2 * (ts[1] - ts[0])
