@@ -1,0 +1,228 @@
+"""Benchmark: one step = the whole hot path over the full FP64 ensemble
+(1e6 neon atoms, charge states 1..10, ~1e7 electron slots, radially polarized
+focus 0.8 um / w0 3 um / 30 fs / 1e21 W/cm^2, field order 5, dt = T/200):
+sample atoms -> ionization times -> FP64 push -> energy-angle histogram, all
+on one MI355X.  Prints ONE JSON line on stdout; progress goes to stderr.
+
+value = electron-steps of the step / wall time of the step (GPU events around
+the timed region, inputs resident in HBM).  The same run also times the mixed
+FP32/FP64 push on the same birth times and reports its speedup and energy
+error against the FP64 push, the FP64 push kernel's roofline fraction
+(algorithmic FP64 FLOPs per electron-step x electron-steps / kernel time,
+against the MI355X FP64 vector peak) and the CPU oracle's rate on a bounded
+sample of the same ensemble.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+C_LIGHT = 299792458.0
+# FP64 operations per electron-step of the order-5 push (mul, add = 1, fma = 2;
+# special functions at the cost of their standard polynomial implementations).
+ALGO_FLOP_PER_STEP = 1041.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+PROFILE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_fp64_rp_ne_fp64_1m_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def electron_steps(tb, z, K, L):
+    """Number of RK4 steps the push takes for every born slot (ceil of the
+    window remainder over dt), summed -- the unit of the metric."""
+    import torch
+    fin = torch.isfinite(tb)
+    zz = z.repeat_interleave(K)
+    tz = zz / C_LIGHT if L.window == 0 else torch.zeros_like(zz)
+    n = torch.ceil(((tz + L.t_after) - tb) / L.dt)
+    return int(n[fin].clamp(min=0).sum().item()), int(fin.sum().item())
+
+
+def cpu_baseline(ens, budget_s=15.0):
+    """Oracle push rate on a bounded sample of the same ensemble (the slots of
+    the first atoms, with the GPU's birth times), scaled to ~budget_s."""
+    import numpy as np
+    import oracle as O
+    rec = ens.wl["lasers"][0]
+    OL = O.laser_intensity(rec["lam"], rec["w0"], rec["tau"], rec["I"])
+    OL.field = ens.L.field
+    K = ens.K
+    tb = ens.tb.cpu().numpy()
+    x, y, z = (a.cpu().numpy() for a in (ens.x, ens.y, ens.z))
+
+    def run(na):
+        t = tb[: na * K]
+        fin = np.isfinite(t)
+        steps = np.ceil((np.repeat(z[:na], K)[fin] / C_LIGHT + OL.t_after - t[fin]) / OL.dt).sum()
+        t0 = time.perf_counter()
+        O.push(OL, t, x[:na], y[:na], z[:na], K)
+        return float(steps), time.perf_counter() - t0
+
+    s1, t1 = run(4)
+    na = int(max(4, min(len(x), 4 * budget_s / max(t1, 1e-3))))
+    s2, t2 = run(na)
+    return dict(value=s2 / t2, unit="electron-steps/s", cores=O.num_threads(), kind="oracle",
+                sample=f"FP64 push of the slots of the first {na} atoms ({int(s2)} electron-steps, "
+                       f"{t2:.1f} s) with the GPU's birth times; order-5 field, same laser")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--atoms", type=int, default=None, help="override (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "design (atom chunks per GPU, one all-reduce of the integer histograms) is not "
+              "built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2509_01741_amd import binding as B
+    from paper_2509_01741_amd import pipeline, workloads
+
+    torch.cuda.set_device(0)
+    wl = workloads.FULL_FP64
+    ens = pipeline.Ensemble(wl, precision=B.RPDLA_FP64, n_atoms=args.atoms)
+    log(f"workload {wl['name']}: {ens.n} atoms x {ens.K} states = {ens.n * ens.K} slots")
+
+    for i in range(args.warmup):
+        t0 = time.time()
+        ens.step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup}: {time.time() - t0:.2f} s")
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start = ev()
+    t_start.record()
+    push_ms, ion_ms = [], []
+    for i in range(args.steps):
+        a, b, c = ev(), ev(), ev()
+        ens.sample()
+        a.record()
+        ens.ionize()
+        b.record()
+        ens.push()
+        c.record()
+        ens.histogram()
+        push_ms.append((b, c))
+        ion_ms.append((a, b))
+        c.synchronize()
+        log(f"step {i + 1}/{args.steps}: ionize {a.elapsed_time(b):.1f} ms, push {b.elapsed_time(c):.1f} ms")
+    t_end = ev()
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    push_avg = sum(b.elapsed_time(c) for b, c in push_ms) / len(push_ms)
+    ion_avg = sum(a.elapsed_time(b) for a, b in ion_ms) / len(ion_ms)
+    steps, born = electron_steps(ens.tb, ens.z, ens.K, ens.L)
+    ms_per_step = total_ms / args.steps
+    value = steps / (ms_per_step * 1e-3)
+    push_rate = steps / (push_avg * 1e-3)
+    achieved_tflops = ALGO_FLOP_PER_STEP * steps / (push_avg * 1e-3) / 1e12
+    tal = ens.tallies.cpu().tolist()
+    log(f"{steps:.4e} electron-steps over {born} electrons; step {ms_per_step:.1f} ms; "
+        f"push {push_rate:.3e} e-steps/s = {achieved_tflops:.1f} TFLOP/s")
+
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC_FILE):
+        try:
+            tr = json.load(open(PROFILE_TRAFFIC_FILE))
+            traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    mixed = None
+    if not args.no_mixed:
+        outs = tuple(torch.empty_like(o) for o in ens.out)
+        B.rpdla_push(ens.L, B.RPDLA_MIXED, ens.tb, ens.x, ens.y, ens.z, ens.K, outs)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        B.rpdla_push(ens.L, B.RPDLA_MIXED, ens.tb, ens.x, ens.y, ens.z, ens.K, outs)
+        b.record()
+        torch.cuda.synchronize()
+        mix_ms = a.elapsed_time(b)
+        fin = torch.isfinite(ens.tb)
+
+        def kin(o):
+            u2 = o[0][fin] ** 2 + o[1][fin] ** 2 + o[2][fin] ** 2
+            return 0.51099895 * u2 / (torch.sqrt(1 + u2) + 1), o[2][fin] > 0
+
+        K64, f64 = kin(ens.out)
+        Kmx, fmx = kin(outs)
+        rel = (Kmx - K64).abs() / K64
+        mixed = dict(
+            push_ms=round(mix_ms, 2),
+            electron_steps_per_s=steps / (mix_ms * 1e-3),
+            speedup_vs_fp64=push_avg / mix_ms,
+            frac_rel_err_le_1e3=float((rel <= 1e-3).double().mean().item()),
+            median_rel_err=float(rel.median().item()),
+            p99_rel_err=float(torch.quantile(rel[:1_000_000].double(), 0.99).item()),
+            mean_energy_rel_err=float((Kmx.double().mean() / K64.double().mean() - 1).item()),
+            same_direction=float((f64 == fmx).double().mean().item()),
+        )
+        log(f"mixed: {mixed}")
+
+    base = None
+    if not args.no_cpu_baseline:
+        try:
+            base = cpu_baseline(ens)
+            log(f"cpu baseline: {base['value']:.3e} e-steps/s on {base['cores']} threads")
+        except Exception as e:  # the oracle is a reported baseline only
+            log(f"cpu baseline unavailable: {e!r}")
+
+    rec = wl["lasers"][0]
+    out = {
+        "metric": "electron-steps/s (FP64 full Monte Carlo step: sample, ionize, push, histogram)",
+        "value": value,
+        "unit": "electron-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl["name"], "atoms": ens.n, "charge_states": [wl["k_first"], wl["k_last"]],
+            "slots": ens.n * ens.K, "born_electrons": born, "electron_steps": steps,
+            "lambda_um": rec["lam"] * 1e6, "w0_um": rec["w0"] * 1e6, "tau_fwhm_fs": rec["tau"] * 1e15,
+            "I_W_cm2": rec["I"], "field_order": int(ens.L.field), "dt": "T/200",
+            "window": "[z/c - 5 tau, z/c + 10 tau]",
+        },
+        "roofline": {
+            "bound": "alu", "kernel": "push_kernel<5, ElecF64>",
+            "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+            "flop_per_electron_step": ALGO_FLOP_PER_STEP, "push_ms": round(push_avg, 2),
+        },
+        "push_electron_steps_per_s": push_rate,
+        "ionize_ms": round(ion_avg, 2),
+        "tallies": dict(zip(["fwd", "bwd", "below", "above", "unborn", "nan"], tal)),
+        "mixed": mixed,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

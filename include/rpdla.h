@@ -1,0 +1,230 @@
+/*
+ * rpdla.h -- C ABI of the MI355X (gfx950) library for the ionization-seeded
+ * direct-laser-acceleration Monte Carlo of arXiv 2509.01741 ("Forward and
+ * backward electron acceleration by radially polarized ultra-intense laser
+ * focus seeded by field ionization of high charge states of neon").
+ *
+ * The path: neon atoms sampled over the focal volume (Sec. 2.1 "Ionization"),
+ * field-ionized charge state by charge state with a semi-classical tunnelling
+ * rate (Sec. 1, Sec. 2.1), every freed electron born at rest and pushed
+ * through the radially polarized focus (Eqs. (1)-(2) and B_theta, with the
+ * w0/z_r corrections of Sec. 2.1) by the Newton-Lorentz equations
+ * (Eqs. (7)-(14)), then binned by final energy ((gamma-1) m c^2, text after
+ * Eq. (14)) and emission angle, split forward / backward (Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *   - SI units unless stated.
+ *   - Array arguments are DEVICE pointers owned by the caller (for example
+ *     torch tensors' data_ptr()).  The library never frees them and keeps no
+ *     reference after the call has been enqueued.  Struct arguments
+ *     (rpdla_laser, rpdla_hist_spec) are HOST pointers read during the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued asynchronously on it; the call returns after
+ *     validation and enqueue.  Faults inside kernels surface at the caller's
+ *     next synchronization.
+ *   - Every entry point validates its arguments before enqueueing anything
+ *     and returns RPDLA_EINVAL (nothing enqueued) on bad input;
+ *     rpdla_last_error() then holds a thread-local description.
+ *   - No C++ exception crosses the ABI.  Calls are reentrant; two calls on
+ *     different streams may run concurrently.
+ *   - Random numbers: Philox4x64-10 (Salmon et al., SC'11) with key
+ *     (seed, cfg_id) and counter (atom index, j/4, 0, 0), word j%4, mapped to
+ *     (m+1) 2^-53 with m the top 53 bits.  Stream j = 0, 1, 2 places the atom;
+ *     j = k + 2 is the Exp(1) threshold -ln u of charge state k.  Any atom
+ *     range therefore gives the same numbers however the ensemble is split.
+ */
+#ifndef RPDLA_H
+#define RPDLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RPDLA_OK = 0,
+    RPDLA_EINVAL = -1,       /* invalid argument; nothing enqueued            */
+    RPDLA_ERANGE = -2,       /* size out of the supported range                */
+    RPDLA_EHIP = -3,         /* HIP runtime error at launch / allocation       */
+    RPDLA_ENOMEM = -4,       /* workspace too small or allocation failed       */
+    RPDLA_EUNSUPPORTED = -5  /* combination not implemented                    */
+} rpdla_status;
+
+/* Field model.  RP_O1/O3/O5: radially polarized TM01 focus truncated at
+ * order 1, 3, 5 of the series in eps = w0/z_r (order 1 is Eqs. (1)-(2) of
+ * Sec. 2.1 with the Maxwell-consistent Ez sign; orders 3 and 5 are the
+ * non-paraxial corrections the same section names).  The rest are test
+ * models: PLANE_LP, Ex = A env cos(omega t - k z + phi0), By = Ex/c;
+ * UNIFORM_EB, static fields test_E, test_B. */
+typedef enum {
+    RPDLA_RP_O1 = 1, RPDLA_RP_O3 = 3, RPDLA_RP_O5 = 5,
+    RPDLA_PLANE_LP = 10, RPDLA_UNIFORM_EB = 11
+} rpdla_field;
+
+typedef enum { RPDLA_FP64 = 0, RPDLA_MIXED = 1 } rpdla_precision;
+
+/* Integration window of an atom at axial position z: ARRIVAL,
+ * [z/c - t_before, z/c + t_after] (around the pulse's arrival at the atom);
+ * LAB, [-t_before, t_after]. */
+typedef enum { RPDLA_WIN_ARRIVAL = 0, RPDLA_WIN_LAB = 1 } rpdla_window;
+
+typedef enum { RPDLA_ANG_POLAR = 0, RPDLA_ANG_AZIMUTH = 1 } rpdla_angle;
+
+/* One laser configuration (SI).  Filled by rpdla_laser_init_*, then editable. */
+typedef struct {
+    double lambda;      /* wavelength [m]                                          */
+    double w0;          /* waist radius r0 [m]; z_r = k w0^2 / 2                   */
+    double tau_fwhm;    /* intensity FWHM [s]; envelope exp(-(t-z/c)^2/tau0^2),
+                           tau0 = tau_fwhm / sqrt(2 ln 2)                          */
+    double amp;         /* A, the E0 of Eq. (1) [V/m]                              */
+    double phi0;        /* carrier phase: cos(omega t - k z + ... + phi0)          */
+    int32_t field;      /* rpdla_field                                             */
+    int32_t window;     /* rpdla_window                                            */
+    double t_before;    /* window start before the reference time [s]; default 5 tau */
+    double t_after;     /* window end after the reference time [s]; default 10 tau */
+    double dt;          /* RK4 step and ionization panel width [s]; default T/200  */
+    double ez_scale;    /* multiplies Ez (Sec. 2.2, Fig. 9 study); default 1       */
+    double er_scale;    /* multiplies Ex, Ey; default 1                            */
+    double test_E[3];   /* UNIFORM_EB only [V/m]                                   */
+    double test_B[3];   /* UNIFORM_EB only [T]                                     */
+} rpdla_laser;
+
+/* Energy-angle histogram layout: counts[dir][iE][iA], dir 0 forward (u_z > 0
+ * at the end of the window), 1 backward; iE = floor((log10 K[MeV] -
+ * logE_min_MeV) / width) with width = (logE_max - logE_min)/nE; iA over
+ * [0, pi] (POLAR, atan2(|u_perp|, u_z)) or (-pi, pi] (AZIMUTH, atan2(u_y,
+ * u_x), Sec. 2.2 Fig. 5), top edge folded into the last bin.  Energies
+ * outside the range go to tallies, not to the edge bins. */
+typedef struct {
+    int32_t nE, nA;
+    double logE_min_MeV, logE_max_MeV;
+    int32_t angle;      /* rpdla_angle */
+} rpdla_hist_spec;
+
+/* Tallies, uint64[6]: 0 forward, 1 backward (born, finite), 2 below the energy
+ * range, 3 above it, 4 unborn slots, 5 born slots with a NaN momentum. */
+#define RPDLA_NTALLY 6
+
+/* ------------------------------------------------------------------------
+ * Laser set-up (host only, no device work).
+ * Intensity: A = sqrt(2 I / (eps0 c)), the Gaussian-equivalent field Sec. 2.1
+ * attaches to every quoted intensity (5e19 W/cm^2 -> 1.94e13 V/m).
+ * Power: A = sqrt(8 P / (pi w0^2 eps0 c)), the order-1 beam's power.
+ * Defaults: field RP_O5, window ARRIVAL, t_before 5 tau, t_after 10 tau,
+ * dt = lambda/(200 c), phi0 0, unit scales.  EINVAL on non-positive input.
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_laser_init_intensity(rpdla_laser* L, double lambda, double w0,
+                                        double tau_fwhm, double I_W_cm2);
+rpdla_status rpdla_laser_init_power(rpdla_laser* L, double lambda, double w0,
+                                    double tau_fwhm, double P_W);
+
+/* Rayleigh length z_r = k w0^2 / 2 [m] (definition under Eq. (2)). */
+double rpdla_rayleigh(const rpdla_laser* L);
+
+/* ------------------------------------------------------------------------
+ * Atom sampling (Sec. 2.1: ions at rest, uniform in a cylinder about the
+ * propagation axis, focus at the origin).  Atom i = first_atom + j:
+ * r = r_max sqrt(u0), azimuth 2 pi u1, z = z_half (2 u2 - 1).
+ * x, y, z: device double[n_atoms], written.  EINVAL: n_atoms < 0, null
+ * pointers with n_atoms > 0, r_max or z_half negative or non-finite.
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_sample_atoms(uint64_t seed, uint32_t cfg_id, uint64_t first_atom,
+                                int64_t n_atoms, double r_max, double z_half,
+                                double* x, double* y, double* z, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Ionization times (Sec. 2.1 "Ionization": charge states freed one after
+ * another, t0 the birth time).  For atom i (index first_atom + j, position
+ * x[j], y[j], z[j]) and states k = k_first..k_last in order, state k is born
+ * when the integral of the static ADK rate w_k(|E(x_i, t)|) since the previous
+ * birth (the window start for k_first) reaches -ln u_{k+2}; the integral is
+ * GL-4 on panels of width dt laid from the window start, the crossing solved
+ * inside its panel by bracketed Newton.  ADK: l = m = 0, l* = n* - 1, neon
+ * potentials, w = 0 where ln w[1/s] < -700.
+ * t_birth: device double[n_atoms * K], K = k_last - k_first + 1, atom-major
+ * (slot j*K + (k - k_first)), seconds, +INF where the state is not reached
+ * in the window.  EINVAL: bad laser, 1 <= k_first <= k_last <= 10 violated,
+ * null pointers with n_atoms > 0.
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_ionize(const rpdla_laser* L, uint64_t seed, uint32_t cfg_id,
+                          uint64_t first_atom, int64_t n_atoms, const double* x,
+                          const double* y, const double* z, int32_t k_first,
+                          int32_t k_last, double* t_birth, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Push (Eqs. (7)-(14), radiation reaction dropped as in the paper below
+ * 5e22 W/cm^2).  Slot s belongs to atom s / slots_per_atom, whose position is
+ * x0/y0/z0[s / slots_per_atom]; the electron starts at rest there at
+ * t_birth[s] and is advanced by classical RK4 with fixed step dt (steps
+ * start at t_birth + n dt, the last one ends on the window end) to the end
+ * of its atom's window.  u = p/(m c).
+ * Outputs, device double[n_slots]: ux, uy, uz and final position xf, yf, zf
+ * [m]; all six NaN for unborn slots (t_birth = +INF or NaN) and for births
+ * earlier than one step before the window start (invalid input; this also
+ * bounds every lane's step count).
+ * precision RPDLA_FP64: everything in double.  RPDLA_MIXED: field and RK4
+ * stages in float; time, position and the carrier phase in double (phase
+ * reduced to one turn before the float sine / cosine); momentum accumulated
+ * in float with Kahan compensation.
+ * EINVAL: bad laser, n_slots < 0, slots_per_atom < 1, null pointers with
+ * n_slots > 0.  Uses a small stream-ordered device allocation for its work
+ * queue (RPDLA_EHIP if that fails).
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots,
+                        const double* t_birth, const double* x0, const double* y0,
+                        const double* z0, int32_t slots_per_atom, double* ux, double* uy,
+                        double* uz, double* xf, double* yf, double* zf, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Energy-angle histogram of n_slots electrons (see rpdla_hist_spec).
+ * t_birth (to recognise unborn slots), ux, uy, uz: device double[n_slots].
+ * counts: device uint64[2 * nE * nA] and tallies: device uint64[6], both
+ * ACCUMULATED into (clear them first for a fresh histogram).  Wave-level
+ * aggregation before the global atomics.  EINVAL: nE, nA < 1, min >= max,
+ * null pointers.
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_histogram(int64_t n_slots, const double* t_birth, const double* ux,
+                             const double* uy, const double* uz, const rpdla_hist_spec* spec,
+                             uint64_t* counts, uint64_t* tallies, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched sweep: n_cfg laser configurations (host array cfgs[n_cfg]), each
+ * with atoms_per_cfg atoms sampled uniformly in r < r_factor * w0,
+ * |z| < z_r, RNG key (seed, cfg_base + c) for configuration c, charge states
+ * k_first..k_last.  Atoms are processed in chunks of atoms_per_chunk per
+ * configuration; each chunk runs sample -> ionize -> push -> histogram, the
+ * push as ONE persistent launch over every configuration's electrons (one
+ * global work queue, lanes refilled as their electron finishes; the
+ * configuration table staged in LDS), the push epilogue binned directly.
+ * The chunk's launch sequence is captured once in a hipGraph and replayed.
+ * counts: device uint64[n_cfg][2][nE][nA], tallies: device uint64[n_cfg][6],
+ * accumulated.  workspace: device memory of at least
+ * rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last)
+ * bytes, 256-byte aligned, owned by the caller, not touched by other work
+ * until the stream reaches the end of this call.
+ * EINVAL on bad configurations or sizes; RPDLA_ENOMEM when ws_bytes is too
+ * small; RPDLA_EUNSUPPORTED for n_cfg > 64.
+ * ------------------------------------------------------------------------ */
+size_t rpdla_batched_workspace_bytes(int32_t n_cfg, int64_t atoms_per_chunk, int32_t k_first,
+                                     int32_t k_last);
+rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t seed,
+                               uint32_t cfg_base, int64_t atoms_per_cfg, int64_t atoms_per_chunk,
+                               double r_factor, int32_t k_first, int32_t k_last,
+                               int32_t precision, const rpdla_hist_spec* spec,
+                               uint64_t* counts, uint64_t* tallies, void* workspace,
+                               size_t ws_bytes, void* stream);
+
+/* Status text and the calling thread's last error detail (never NULL). */
+const char* rpdla_status_string(rpdla_status s);
+const char* rpdla_last_error(void);
+
+/* Library version string. */
+const char* rpdla_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPDLA_H */

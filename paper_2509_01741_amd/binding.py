@@ -1,0 +1,218 @@
+"""Python binding of the C ABI in ``include/rpdla.h`` (argument marshalling
+only).  Every function has the C name; arrays are torch CUDA tensors (device
+memory), the stream is torch's current stream unless one is given.  All the
+arithmetic happens in the gfx950 kernels of ``librpdla.so``: if the library
+is missing the import fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librpdla.so")
+
+RPDLA_OK, RPDLA_EINVAL, RPDLA_ERANGE, RPDLA_EHIP, RPDLA_ENOMEM, RPDLA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+RPDLA_RP_O1, RPDLA_RP_O3, RPDLA_RP_O5, RPDLA_PLANE_LP, RPDLA_UNIFORM_EB = 1, 3, 5, 10, 11
+RPDLA_FP64, RPDLA_MIXED = 0, 1
+RPDLA_WIN_ARRIVAL, RPDLA_WIN_LAB = 0, 1
+RPDLA_ANG_POLAR, RPDLA_ANG_AZIMUTH = 0, 1
+RPDLA_NTALLY = 6
+
+
+class RpdlaError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+class rpdla_laser(C.Structure):
+    _fields_ = [
+        ("lambda_", C.c_double), ("w0", C.c_double), ("tau_fwhm", C.c_double),
+        ("amp", C.c_double), ("phi0", C.c_double),
+        ("field", C.c_int32), ("window", C.c_int32),
+        ("t_before", C.c_double), ("t_after", C.c_double), ("dt", C.c_double),
+        ("ez_scale", C.c_double), ("er_scale", C.c_double),
+        ("test_E", C.c_double * 3), ("test_B", C.c_double * 3),
+    ]
+
+    def set(self, **kw):
+        for k, v in kw.items():
+            if k in ("test_E", "test_B"):
+                getattr(self, k)[:] = [float(a) for a in v]
+            elif k in ("lam", "lambda"):
+                self.lambda_ = float(v)
+            else:
+                setattr(self, k, v)
+        return self
+
+
+class rpdla_hist_spec(C.Structure):
+    _fields_ = [("nE", C.c_int32), ("nA", C.c_int32), ("logE_min_MeV", C.c_double),
+                ("logE_max_MeV", C.c_double), ("angle", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built: run `python -m paper_2509_01741_amd.build` "
+            "(hipcc, gfx950); the library has no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+    LP = C.POINTER(rpdla_laser)
+    HP = C.POINTER(rpdla_hist_spec)
+    sig = {
+        "rpdla_laser_init_intensity": (i32, [LP, d, d, d, d]),
+        "rpdla_laser_init_power": (i32, [LP, d, d, d, d]),
+        "rpdla_rayleigh": (d, [LP]),
+        "rpdla_sample_atoms": (i32, [u64, u32, u64, i64, d, d, vp, vp, vp, vp]),
+        "rpdla_ionize": (i32, [LP, u64, u32, u64, i64, vp, vp, vp, i32, i32, vp, vp]),
+        "rpdla_push": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
+        "rpdla_batched_workspace_bytes": (C.c_size_t, [i32, i64, i32, i32]),
+        "rpdla_run_batched": (i32, [LP, i32, u64, u32, i64, i64, d, i32, i32, i32, HP, vp, vp,
+                                    vp, C.c_size_t, vp]),
+        "rpdla_status_string": (C.c_char_p, [i32]),
+        "rpdla_last_error": (C.c_char_p, []),
+        "rpdla_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int, where: str):
+    if status != RPDLA_OK:
+        raise RpdlaError(status, where, lib.rpdla_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev(t: torch.Tensor, name: str, n: int, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, need {n}")
+    return C.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+def _empty(n, like=None, dtype=torch.float64, device=None):
+    dev = device if device is not None else (like.device if like is not None else "cuda")
+    return torch.empty(n, dtype=dtype, device=dev)
+
+
+def rpdla_version() -> str:
+    return lib.rpdla_version().decode()
+
+
+def rpdla_laser_init_intensity(lam, w0, tau_fwhm, I_W_cm2, **kw) -> rpdla_laser:
+    L = rpdla_laser()
+    _check(lib.rpdla_laser_init_intensity(C.byref(L), lam, w0, tau_fwhm, I_W_cm2),
+           "rpdla_laser_init_intensity")
+    return L.set(**kw)
+
+
+def rpdla_laser_init_power(lam, w0, tau_fwhm, P_W, **kw) -> rpdla_laser:
+    L = rpdla_laser()
+    _check(lib.rpdla_laser_init_power(C.byref(L), lam, w0, tau_fwhm, P_W), "rpdla_laser_init_power")
+    return L.set(**kw)
+
+
+def rpdla_rayleigh(L: rpdla_laser) -> float:
+    return lib.rpdla_rayleigh(C.byref(L))
+
+
+def rpdla_sample_atoms(seed, cfg_id, first_atom, n_atoms, r_max, z_half, x=None, y=None, z=None,
+                       stream=None, device=None):
+    x = _empty(n_atoms, device=device) if x is None else x
+    y = _empty(n_atoms, like=x) if y is None else y
+    z = _empty(n_atoms, like=x) if z is None else z
+    _check(lib.rpdla_sample_atoms(seed, cfg_id, first_atom, n_atoms, r_max, z_half,
+                                  _dev(x, "x", n_atoms), _dev(y, "y", n_atoms),
+                                  _dev(z, "z", n_atoms), _stream(stream)), "rpdla_sample_atoms")
+    return x, y, z
+
+
+def rpdla_ionize(L, seed, cfg_id, first_atom, x, y, z, k_first, k_last, t_birth=None, stream=None):
+    n = x.numel()
+    K = k_last - k_first + 1
+    t_birth = _empty(n * K, like=x) if t_birth is None else t_birth
+    _check(lib.rpdla_ionize(C.byref(L), seed, cfg_id, first_atom, n, _dev(x, "x", n),
+                            _dev(y, "y", n), _dev(z, "z", n), k_first, k_last,
+                            _dev(t_birth, "t_birth", n * K), _stream(stream)), "rpdla_ionize")
+    return t_birth
+
+
+def rpdla_push(L, precision, t_birth, x0, y0, z0, slots_per_atom, out=None, stream=None):
+    n = t_birth.numel()
+    na = (n + slots_per_atom - 1) // slots_per_atom
+    if out is None:
+        out = tuple(_empty(n, like=t_birth) for _ in range(6))
+    ux, uy, uz, xf, yf, zf = out
+    _check(lib.rpdla_push(C.byref(L), precision, n, _dev(t_birth, "t_birth", n),
+                          _dev(x0, "x0", na), _dev(y0, "y0", na), _dev(z0, "z0", na),
+                          slots_per_atom, _dev(ux, "ux", n), _dev(uy, "uy", n), _dev(uz, "uz", n),
+                          _dev(xf, "xf", n), _dev(yf, "yf", n), _dev(zf, "zf", n),
+                          _stream(stream)), "rpdla_push")
+    return out
+
+
+def rpdla_histogram(t_birth, ux, uy, uz, spec: rpdla_hist_spec, counts=None, tallies=None,
+                    stream=None):
+    """counts: int64 tensor [2, nE, nA] and tallies: int64 tensor [6] (the
+    library adds unsigned 64-bit counts into them)."""
+    n = t_birth.numel()
+    nb = 2 * spec.nE * spec.nA
+    if counts is None:
+        counts = torch.zeros((2, spec.nE, spec.nA), dtype=torch.int64, device=t_birth.device)
+    if tallies is None:
+        tallies = torch.zeros(RPDLA_NTALLY, dtype=torch.int64, device=t_birth.device)
+    _check(lib.rpdla_histogram(n, _dev(t_birth, "t_birth", n), _dev(ux, "ux", n),
+                               _dev(uy, "uy", n), _dev(uz, "uz", n), C.byref(spec),
+                               _dev(counts, "counts", nb, torch.int64),
+                               _dev(tallies, "tallies", RPDLA_NTALLY, torch.int64),
+                               _stream(stream)), "rpdla_histogram")
+    return counts, tallies
+
+
+def rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last) -> int:
+    return int(lib.rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last))
+
+
+def rpdla_run_batched(lasers, seed, cfg_base, atoms_per_cfg, atoms_per_chunk, r_factor, k_first,
+                      k_last, precision, spec: rpdla_hist_spec, counts=None, tallies=None,
+                      workspace=None, stream=None, device=None):
+    n_cfg = len(lasers)
+    arr = (rpdla_laser * n_cfg)(*lasers)
+    nb = 2 * spec.nE * spec.nA
+    dev = device if device is not None else "cuda"
+    if counts is None:
+        counts = torch.zeros((n_cfg, 2, spec.nE, spec.nA), dtype=torch.int64, device=dev)
+    if tallies is None:
+        tallies = torch.zeros((n_cfg, RPDLA_NTALLY), dtype=torch.int64, device=dev)
+    need = rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=counts.device)
+    _check(lib.rpdla_run_batched(arr, n_cfg, seed, cfg_base, atoms_per_cfg, atoms_per_chunk,
+                                 r_factor, k_first, k_last, precision, C.byref(spec),
+                                 _dev(counts, "counts", n_cfg * nb, torch.int64),
+                                 _dev(tallies, "tallies", n_cfg * RPDLA_NTALLY, torch.int64),
+                                 _dev(workspace, "workspace", need, torch.uint8),
+                                 C.c_size_t(workspace.numel()), _stream(stream)),
+           "rpdla_run_batched")
+    return counts, tallies

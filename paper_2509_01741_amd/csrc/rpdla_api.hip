@@ -1,0 +1,561 @@
+// rpdla_api.hip -- host side of the C ABI declared in include/rpdla.h:
+// argument validation, the per-configuration constants in normalized units,
+// kernel dispatch and launch shapes.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rpdla.h"
+#include "rpdla_kernels.hpp"
+#include "rpdla_batched.hpp"
+
+namespace {
+
+using rpdla::DevCfg;
+
+// CODATA 2018 (SI).
+constexpr double kC = 299792458.0;
+constexpr double kQe = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kMeC2MeV = 0.51099895000;
+constexpr double kEa = 5.14220674763e11;       // atomic unit of field [V/m]
+constexpr double kTauA = 2.4188843265857e-17;  // atomic unit of time [s]
+constexpr double kEhEv = 27.211386245988;      // Hartree [eV]
+constexpr double kPi = 3.14159265358979323846;
+
+// Neon ionization potentials Ne^(k-1)+ -> Ne^k+ [eV] (NIST ASD).
+constexpr double kNeIpEv[10] = {21.564540, 40.96297, 63.4233, 97.1900, 126.247,
+                                157.934,   207.271,  239.0970, 1195.80784, 1362.19911};
+
+thread_local std::string g_err;
+
+rpdla_status fail(rpdla_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define RPDLA_HIP(call)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) return fail(RPDLA_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_fin(double v) { return isfinite(v) != 0; }
+
+rpdla_status check_laser(const rpdla_laser* L)
+{
+    if (!L) return fail(RPDLA_EINVAL, "laser is NULL");
+    if (!(is_fin(L->lambda) && L->lambda > 0)) return fail(RPDLA_EINVAL, "lambda must be > 0");
+    if (!(is_fin(L->w0) && L->w0 > 0)) return fail(RPDLA_EINVAL, "w0 must be > 0");
+    if (!(is_fin(L->tau_fwhm) && L->tau_fwhm > 0)) return fail(RPDLA_EINVAL, "tau_fwhm must be > 0");
+    if (!(is_fin(L->amp) && L->amp >= 0)) return fail(RPDLA_EINVAL, "amp must be >= 0");
+    if (!(is_fin(L->dt) && L->dt > 0)) return fail(RPDLA_EINVAL, "dt must be > 0");
+    if (!(is_fin(L->t_before) && is_fin(L->t_after) && L->t_before > 0 && L->t_after > 0))
+        return fail(RPDLA_EINVAL, "window must contain the pulse peak (t_before, t_after > 0)");
+    if (!(is_fin(L->phi0) && is_fin(L->ez_scale) && is_fin(L->er_scale)))
+        return fail(RPDLA_EINVAL, "phi0 and the field scales must be finite");
+    const int f = L->field;
+    if (!(f == RPDLA_RP_O1 || f == RPDLA_RP_O3 || f == RPDLA_RP_O5 || f == RPDLA_PLANE_LP ||
+          f == RPDLA_UNIFORM_EB))
+        return fail(RPDLA_EINVAL, "unknown field model %d", f);
+    if (!(L->window == RPDLA_WIN_ARRIVAL || L->window == RPDLA_WIN_LAB))
+        return fail(RPDLA_EINVAL, "unknown window %d", L->window);
+    for (int i = 0; i < 3; ++i)
+        if (!(is_fin(L->test_E[i]) && is_fin(L->test_B[i])))
+            return fail(RPDLA_EINVAL, "test fields must be finite");
+    const double panels = (L->t_before + L->t_after) / L->dt;
+    if (!(panels < 2.0e9)) return fail(RPDLA_ERANGE, "window / dt = %.3g steps is too many", panels);
+    return RPDLA_OK;
+}
+
+// Rate ln w[normalized] = c0 - c1h ln a2 - c2 a2^(-1/2); |a|^2 where it first
+// reaches `level` on its rising branch (INF if it never does).
+double adk_threshold_a2(double c0, double c1h, double c2, double level)
+{
+    auto f = [&](double la2) { return c0 - c1h * la2 - c2 * exp(-0.5 * la2); };
+    double hi = (c1h > 0) ? 2.0 * log(0.5 * c2 / c1h) : 300.0;  // ln a2 at the rate's peak
+    if (hi > 300.0) hi = 300.0;
+    if (f(hi) < level) return INFINITY;
+    double lo = -300.0;
+    if (f(lo) >= level) return 0.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (f(mid) < level) lo = mid; else hi = mid;
+    }
+    return exp(lo);
+}
+
+DevCfg make_cfg(const rpdla_laser* L)
+{
+    DevCfg c;
+    memset(&c, 0, sizeof c);
+    const double k = 2.0 * kPi / L->lambda;
+    const double om = kC * k;
+    const double w0n = k * L->w0;
+    const double zrn = 0.5 * w0n * w0n;  // k z_r, z_r = k w0^2 / 2
+    const double tau0 = L->tau_fwhm / sqrt(2.0 * log(2.0));
+    c.omega = om; c.inv_omega = 1.0 / om;
+    c.k = k; c.inv_k = 1.0 / k;
+    c.a0 = kQe * L->amp / (kMe * kC * om);
+    c.inv_w0n2 = 1.0 / (w0n * w0n);
+    c.inv_w0n = 1.0 / w0n;
+    c.inv_zrn = 1.0 / zrn;
+    c.eps = 2.0 / w0n;
+    c.e2 = c.eps * c.eps; c.e3 = c.e2 * c.eps; c.e4 = c.e2 * c.e2;
+    c.inv_T0n = 1.0 / (om * tau0);
+    c.phi0 = L->phi0;
+    c.hn = om * L->dt;
+    c.tb_n = om * L->t_before;
+    c.ta_n = om * L->t_after;
+    c.er_scale = L->er_scale; c.ez_scale = L->ez_scale;
+    for (int i = 0; i < 3; ++i) {
+        c.tE[i] = kQe * L->test_E[i] / (kMe * kC * om);
+        c.tB[i] = kQe * L->test_B[i] / (kMe * om);
+    }
+    c.field = L->field; c.window = L->window;
+    // tunnelling constants: F [a.u.] = |a| fconv
+    const double fconv = (kMe * kC * om / kQe) / kEa;
+    c.lnw_zero = -700.0 - log(om);
+    for (int s = 0; s < rpdla::kMaxStates; ++s) {
+        const double Ip = kNeIpEv[s] / kEhEv;
+        const double Z = (double)(s + 1);
+        const double ns = Z / sqrt(2.0 * Ip);
+        const double F0 = pow(2.0 * Ip, 1.5);
+        const double lnC2 = 2.0 * ns * log(2.0) - log(ns) - lgamma(2.0 * ns);
+        c.adk_c0[s] = lnC2 + log(Ip / kTauA) + (2.0 * ns - 1.0) * (log(2.0 * F0) - log(fconv)) - log(om);
+        c.adk_c1h[s] = 0.5 * (2.0 * ns - 1.0);
+        c.adk_c2[s] = 2.0 * F0 / (3.0 * fconv);
+        c.adk_a2thr[s] = adk_threshold_a2(c.adk_c0[s], c.adk_c1h[s], c.adk_c2[s], c.lnw_zero - 5.0);
+    }
+    const double ga = sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(6.0 / 5.0));
+    const double gb = sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(6.0 / 5.0));
+    const double wa = (18.0 + sqrt(30.0)) / 36.0, wb = (18.0 - sqrt(30.0)) / 36.0;
+    c.gl_x[0] = -gb; c.gl_x[1] = -ga; c.gl_x[2] = ga; c.gl_x[3] = gb;
+    c.gl_w[0] = wb; c.gl_w[1] = wa; c.gl_w[2] = wa; c.gl_w[3] = wb;
+    return c;
+}
+
+void laser_defaults(rpdla_laser* L, double lambda, double w0, double tau)
+{
+    memset(L, 0, sizeof *L);
+    L->lambda = lambda; L->w0 = w0; L->tau_fwhm = tau;
+    L->phi0 = 0.0;
+    L->field = RPDLA_RP_O5;
+    L->window = RPDLA_WIN_ARRIVAL;
+    L->t_before = 5.0 * tau;
+    L->t_after = 10.0 * tau;
+    L->dt = lambda / kC / 200.0;
+    L->ez_scale = 1.0; L->er_scale = 1.0;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Resident-wave count for a persistent launch of `kernel` with 256 lanes per block.
+template <typename K>
+int persistent_blocks(K kernel, int64_t work_items)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int64_t blocks = (int64_t)cus * per_cu;
+    const int64_t need = cdiv(work_items, 256);
+    if (need < blocks) blocks = need;
+    return (int)(blocks < 1 ? 1 : blocks);
+}
+
+template <int FIELD>
+rpdla_status launch_ionize(const DevCfg& c, uint64_t seed, uint32_t cfg, uint64_t first,
+                           int64_t n, const double* x, const double* y, const double* z, int kf,
+                           int kl, double* tb, hipStream_t st)
+{
+    hipLaunchKernelGGL(rpdla::ionize_kernel<FIELD>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st,
+                       c, seed, cfg, first, n, x, y, z, kf, kl, tb);
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
+template <int FIELD>
+rpdla_status launch_push(const DevCfg& c, int prec, const rpdla::PushIO& io, hipStream_t st)
+{
+    if (prec == RPDLA_FP64) {
+        auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecF64>;
+        const int g = persistent_blocks(kern, io.n_slots);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, st, c, io);
+    } else {
+        auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecMixed>;
+        const int g = persistent_blocks(kern, io.n_slots);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, st, c, io);
+    }
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* rpdla_version(void) { return "rpdla 0.1 (gfx950)"; }
+
+const char* rpdla_status_string(rpdla_status s)
+{
+    switch (s) {
+    case RPDLA_OK: return "ok";
+    case RPDLA_EINVAL: return "invalid argument";
+    case RPDLA_ERANGE: return "size out of range";
+    case RPDLA_EHIP: return "HIP runtime error";
+    case RPDLA_ENOMEM: return "out of memory / workspace too small";
+    case RPDLA_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* rpdla_last_error(void) { return g_err.c_str(); }
+
+rpdla_status rpdla_laser_init_intensity(rpdla_laser* L, double lambda, double w0, double tau,
+                                        double I_W_cm2)
+{
+    if (!L) return fail(RPDLA_EINVAL, "laser is NULL");
+    if (!(lambda > 0 && w0 > 0 && tau > 0 && I_W_cm2 >= 0 && is_fin(lambda) && is_fin(w0) &&
+          is_fin(tau) && is_fin(I_W_cm2)))
+        return fail(RPDLA_EINVAL, "lambda, w0, tau must be > 0 and I >= 0");
+    laser_defaults(L, lambda, w0, tau);
+    L->amp = sqrt(2.0 * I_W_cm2 * 1.0e4 / (kEps0 * kC));
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_laser_init_power(rpdla_laser* L, double lambda, double w0, double tau, double P_W)
+{
+    if (!L) return fail(RPDLA_EINVAL, "laser is NULL");
+    if (!(lambda > 0 && w0 > 0 && tau > 0 && P_W >= 0 && is_fin(lambda) && is_fin(w0) &&
+          is_fin(tau) && is_fin(P_W)))
+        return fail(RPDLA_EINVAL, "lambda, w0, tau must be > 0 and P >= 0");
+    laser_defaults(L, lambda, w0, tau);
+    L->amp = sqrt(8.0 * P_W / (kPi * w0 * w0 * kEps0 * kC));
+    return RPDLA_OK;
+}
+
+double rpdla_rayleigh(const rpdla_laser* L)
+{
+    if (!L) return NAN;
+    const double k = 2.0 * kPi / L->lambda;
+    return 0.5 * k * L->w0 * L->w0;
+}
+
+rpdla_status rpdla_sample_atoms(uint64_t seed, uint32_t cfg_id, uint64_t first_atom, int64_t n,
+                                double r_max, double z_half, double* x, double* y, double* z,
+                                void* stream)
+{
+    if (n < 0) return fail(RPDLA_EINVAL, "n_atoms < 0");
+    if (!(is_fin(r_max) && is_fin(z_half) && r_max >= 0 && z_half >= 0))
+        return fail(RPDLA_EINVAL, "r_max and z_half must be finite and >= 0");
+    if (n == 0) return RPDLA_OK;
+    if (!x || !y || !z) return fail(RPDLA_EINVAL, "null output pointer");
+    if (n > ((int64_t)1 << 40)) return fail(RPDLA_ERANGE, "n_atoms too large");
+    hipLaunchKernelGGL(rpdla::sample_atoms_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0,
+                       (hipStream_t)stream, seed, cfg_id, first_atom, n, r_max, z_half, x, y, z);
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_ionize(const rpdla_laser* L, uint64_t seed, uint32_t cfg_id, uint64_t first_atom,
+                          int64_t n, const double* x, const double* y, const double* z,
+                          int32_t k_first, int32_t k_last, double* t_birth, void* stream)
+{
+    rpdla_status st = check_laser(L);
+    if (st != RPDLA_OK) return st;
+    if (!(1 <= k_first && k_first <= k_last && k_last <= 10))
+        return fail(RPDLA_EINVAL, "need 1 <= k_first <= k_last <= 10 (got %d..%d)", k_first, k_last);
+    if (n < 0) return fail(RPDLA_EINVAL, "n_atoms < 0");
+    if (n == 0) return RPDLA_OK;
+    if (!x || !y || !z || !t_birth) return fail(RPDLA_EINVAL, "null pointer");
+    if (n > ((int64_t)1 << 36)) return fail(RPDLA_ERANGE, "n_atoms too large");
+    const DevCfg c = make_cfg(L);
+    hipStream_t s = (hipStream_t)stream;
+    switch (L->field) {
+    case 1: return launch_ionize<1>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
+    case 3: return launch_ionize<3>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
+    case 5: return launch_ionize<5>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
+    case 10: return launch_ionize<10>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
+    default: return launch_ionize<11>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
+    }
+}
+
+rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots,
+                        const double* t_birth, const double* x0, const double* y0, const double* z0,
+                        int32_t slots_per_atom, double* ux, double* uy, double* uz, double* xf,
+                        double* yf, double* zf, void* stream)
+{
+    rpdla_status st = check_laser(L);
+    if (st != RPDLA_OK) return st;
+    if (!(precision == RPDLA_FP64 || precision == RPDLA_MIXED))
+        return fail(RPDLA_EINVAL, "unknown precision %d", precision);
+    if (n_slots < 0) return fail(RPDLA_EINVAL, "n_slots < 0");
+    if (slots_per_atom < 1) return fail(RPDLA_EINVAL, "slots_per_atom < 1");
+    if (n_slots == 0) return RPDLA_OK;
+    if (!t_birth || !x0 || !y0 || !z0 || !ux || !uy || !uz || !xf || !yf || !zf)
+        return fail(RPDLA_EINVAL, "null pointer");
+    if (n_slots > ((int64_t)1 << 40)) return fail(RPDLA_ERANGE, "n_slots too large");
+    const DevCfg c = make_cfg(L);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* q = nullptr;
+    RPDLA_HIP(hipMallocAsync((void**)&q, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(64), 0, s, q, (int64_t)1);
+    rpdla::PushIO io{t_birth, x0, y0, z0, slots_per_atom, n_slots, ux, uy, uz, xf, yf, zf, q};
+    switch (L->field) {
+    case 1: st = launch_push<1>(c, precision, io, s); break;
+    case 3: st = launch_push<3>(c, precision, io, s); break;
+    case 5: st = launch_push<5>(c, precision, io, s); break;
+    case 10: st = launch_push<10>(c, precision, io, s); break;
+    default: st = launch_push<11>(c, precision, io, s); break;
+    }
+    hipError_t fe = hipFreeAsync(q, s);
+    if (st != RPDLA_OK) return st;
+    if (fe != hipSuccess) return fail(RPDLA_EHIP, "hipFreeAsync: %s", hipGetErrorString(fe));
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_histogram(int64_t n, const double* t_birth, const double* ux, const double* uy,
+                             const double* uz, const rpdla_hist_spec* spec, uint64_t* counts,
+                             uint64_t* tallies, void* stream)
+{
+    if (!spec) return fail(RPDLA_EINVAL, "spec is NULL");
+    if (spec->nE < 1 || spec->nA < 1) return fail(RPDLA_EINVAL, "nE, nA must be >= 1");
+    if (!(is_fin(spec->logE_min_MeV) && is_fin(spec->logE_max_MeV) &&
+          spec->logE_min_MeV < spec->logE_max_MeV))
+        return fail(RPDLA_EINVAL, "need logE_min < logE_max");
+    if (!(spec->angle == RPDLA_ANG_POLAR || spec->angle == RPDLA_ANG_AZIMUTH))
+        return fail(RPDLA_EINVAL, "unknown angle mode");
+    if ((int64_t)spec->nE * spec->nA > ((int64_t)1 << 28)) return fail(RPDLA_ERANGE, "too many bins");
+    if (n < 0) return fail(RPDLA_EINVAL, "n_slots < 0");
+    if (!counts || !tallies) return fail(RPDLA_EINVAL, "null output pointer");
+    if (n == 0) return RPDLA_OK;
+    if (!t_birth || !ux || !uy || !uz) return fail(RPDLA_EINVAL, "null input pointer");
+    rpdla::HistArgs H;
+    H.nE = spec->nE; H.nA = spec->nA; H.angle = spec->angle;
+    H.lo = spec->logE_min_MeV;
+    H.width = (spec->logE_max_MeV - spec->logE_min_MeV) / (double)spec->nE;
+    H.mec2 = kMeC2MeV;
+    int64_t blocks = cdiv(n, 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(rpdla::histogram_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, H, n, t_birth, ux, uy, uz,
+                       (unsigned long long*)counts, (unsigned long long*)tallies);
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched sweep
+// ===========================================================================
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    size_t cfg, geo, ctl, x, y, z, tb, total;
+};
+
+WsLayout ws_layout(int n_cfg, int64_t apc, int K)
+{
+    WsLayout w;
+    size_t off = 0;
+    const size_t na = (size_t)n_cfg * (size_t)apc;
+    w.cfg = off; off += align256((size_t)n_cfg * sizeof(DevCfg));
+    w.geo = off; off += align256((size_t)n_cfg * 2 * sizeof(double));
+    w.ctl = off; off += align256(sizeof(rpdla::BatchCtl));
+    w.x = off; off += align256(na * sizeof(double));
+    w.y = off; off += align256(na * sizeof(double));
+    w.z = off; off += align256(na * sizeof(double));
+    w.tb = off; off += align256(na * (size_t)K * sizeof(double));
+    w.total = off;
+    return w;
+}
+
+std::mutex g_graph_mu;
+std::vector<std::pair<std::string, hipGraphExec_t>> g_graphs;  // small cache, process lifetime
+
+template <int FIELD, class ELEC>
+rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipStream_t s)
+{
+    const size_t lds_i = (size_t)A.n_cfg * sizeof(DevCfg);
+    const size_t lds_p = (size_t)A.n_cfg * (sizeof(rpdla::PushCfg) + 6 * sizeof(unsigned long long));
+    auto* kpush = rpdla::batch_push_kernel<FIELD, ELEC>;
+    auto* kion = rpdla::batch_ionize_kernel<FIELD>;
+    int dev = 0, cus = 0, per_cu = 0;
+    RPDLA_HIP(hipGetDevice(&dev));
+    RPDLA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    RPDLA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kpush, 256, lds_p));
+    if (per_cu < 1) per_cu = 1;
+    const int64_t slots = (int64_t)A.n_cfg * A.apc * A.K;
+    int64_t grid_p = (int64_t)cus * per_cu;
+    if (cdiv(slots, 256) < grid_p) grid_p = cdiv(slots, 256);
+    const unsigned grid_a = (unsigned)cdiv((int64_t)A.n_cfg * A.apc, 256);
+
+    auto enqueue_chunk = [&](hipStream_t st) -> rpdla_status {
+        hipLaunchKernelGGL(rpdla::batch_zero_queue_kernel, dim3(1), dim3(64), 0, st, A.ctl);
+        hipLaunchKernelGGL(rpdla::batch_sample_kernel, dim3(grid_a), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(kion, dim3(grid_a), dim3(256), lds_i, st, A);
+        hipLaunchKernelGGL(kpush, dim3((unsigned)grid_p), dim3(256), lds_p, st, A);
+        hipLaunchKernelGGL(rpdla::batch_advance_kernel, dim3(1), dim3(64), 0, st, A.ctl);
+        RPDLA_HIP(hipGetLastError());
+        return RPDLA_OK;
+    };
+
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (s != nullptr) RPDLA_HIP(hipStreamIsCapturing(s, &cap));
+    if (s == nullptr || cap != hipStreamCaptureStatusNone || n_chunks == 1) {
+        for (int64_t i = 0; i < n_chunks; ++i) {
+            rpdla_status r = enqueue_chunk(s);
+            if (r != RPDLA_OK) return r;
+        }
+        return RPDLA_OK;
+    }
+    // one chunk captured as a graph (kernel arguments fixed; the chunk index
+    // lives in device memory and advances inside the graph), replayed per chunk
+    std::string key(reinterpret_cast<const char*>(&A), sizeof A);
+    const int tag[2] = {FIELD, (int)sizeof(ELEC)};
+    key.append(reinterpret_cast<const char*>(tag), sizeof tag);
+    key.append(reinterpret_cast<const char*>(&s), sizeof s);
+    key.append(reinterpret_cast<const char*>(&grid_p), sizeof grid_p);
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (auto& kv : g_graphs)
+            if (kv.first == key) { exec = kv.second; break; }
+    }
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        RPDLA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        rpdla_status r = enqueue_chunk(s);
+        hipError_t ee = hipStreamEndCapture(s, &graph);
+        if (r != RPDLA_OK) return r;
+        if (ee != hipSuccess) return fail(RPDLA_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(RPDLA_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        g_graphs.emplace_back(key, exec);
+    }
+    for (int64_t i = 0; i < n_chunks; ++i) RPDLA_HIP(hipGraphLaunch(exec, s));
+    return RPDLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rpdla_batched_workspace_bytes(int32_t n_cfg, int64_t atoms_per_chunk, int32_t k_first,
+                                     int32_t k_last)
+{
+    if (n_cfg < 1 || atoms_per_chunk < 1 || k_first < 1 || k_last < k_first || k_last > 10) return 0;
+    return ws_layout(n_cfg, atoms_per_chunk, k_last - k_first + 1).total;
+}
+
+rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t seed,
+                               uint32_t cfg_base, int64_t atoms_per_cfg, int64_t atoms_per_chunk,
+                               double r_factor, int32_t k_first, int32_t k_last, int32_t precision,
+                               const rpdla_hist_spec* spec, uint64_t* counts, uint64_t* tallies,
+                               void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!cfgs) return fail(RPDLA_EINVAL, "cfgs is NULL");
+    if (n_cfg < 1) return fail(RPDLA_EINVAL, "n_cfg must be >= 1");
+    if (n_cfg > 64) return fail(RPDLA_EUNSUPPORTED, "at most 64 configurations per call");
+    for (int c = 0; c < n_cfg; ++c) {
+        rpdla_status st = check_laser(&cfgs[c]);
+        if (st != RPDLA_OK) return fail(st, "configuration %d: %s", c, g_err.c_str());
+        if (cfgs[c].field != cfgs[0].field)
+            return fail(RPDLA_EINVAL, "all configurations must use the same field model");
+    }
+    if (!(precision == RPDLA_FP64 || precision == RPDLA_MIXED))
+        return fail(RPDLA_EINVAL, "unknown precision %d", precision);
+    if (!(1 <= k_first && k_first <= k_last && k_last <= 10))
+        return fail(RPDLA_EINVAL, "need 1 <= k_first <= k_last <= 10");
+    if (atoms_per_cfg < 0) return fail(RPDLA_EINVAL, "atoms_per_cfg < 0");
+    if (atoms_per_chunk < 1) return fail(RPDLA_EINVAL, "atoms_per_chunk must be >= 1");
+    if (!(is_fin(r_factor) && r_factor >= 0)) return fail(RPDLA_EINVAL, "r_factor must be >= 0");
+    if (!spec || spec->nE < 1 || spec->nA < 1 ||
+        !(is_fin(spec->logE_min_MeV) && is_fin(spec->logE_max_MeV) &&
+          spec->logE_min_MeV < spec->logE_max_MeV) ||
+        !(spec->angle == RPDLA_ANG_POLAR || spec->angle == RPDLA_ANG_AZIMUTH))
+        return fail(RPDLA_EINVAL, "invalid histogram spec");
+    if ((int64_t)n_cfg * spec->nE * spec->nA > ((int64_t)1 << 28))
+        return fail(RPDLA_ERANGE, "too many histogram bins");
+    if (!counts || !tallies || !workspace) return fail(RPDLA_EINVAL, "null pointer");
+    if (((uintptr_t)workspace & 255) != 0) return fail(RPDLA_EINVAL, "workspace must be 256-byte aligned");
+    const int K = k_last - k_first + 1;
+    if ((double)n_cfg * (double)atoms_per_chunk * K > 1.0e12)
+        return fail(RPDLA_ERANGE, "chunk too large");
+    const WsLayout w = ws_layout(n_cfg, atoms_per_chunk, K);
+    if (ws_bytes < w.total)
+        return fail(RPDLA_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, w.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)workspace;
+    rpdla::BatchArgs A;
+    memset(&A, 0, sizeof A);
+    A.cfgs = (const DevCfg*)(base + w.cfg);
+    A.geo = (const double*)(base + w.geo);
+    A.n_cfg = n_cfg;
+    A.seed = seed;
+    A.cfg_base = cfg_base;
+    A.atoms_per_cfg = atoms_per_cfg;
+    A.apc = atoms_per_chunk;
+    A.k_first = k_first;
+    A.K = K;
+    A.x = (double*)(base + w.x); A.y = (double*)(base + w.y); A.z = (double*)(base + w.z);
+    A.tb = (double*)(base + w.tb);
+    A.ctl = (rpdla::BatchCtl*)(base + w.ctl);
+    A.H.nE = spec->nE; A.H.nA = spec->nA; A.H.angle = spec->angle;
+    A.H.lo = spec->logE_min_MeV;
+    A.H.width = (spec->logE_max_MeV - spec->logE_min_MeV) / (double)spec->nE;
+    A.H.mec2 = kMeC2MeV;
+    A.counts = (unsigned long long*)counts;
+    A.tallies = (unsigned long long*)tallies;
+    // configuration table: written by tiny kernels (arguments copied at launch)
+    for (int c = 0; c < n_cfg; ++c) {
+        const DevCfg dc = make_cfg(&cfgs[c]);
+        const double rmax = r_factor * cfgs[c].w0;
+        const double zh = rpdla_rayleigh(&cfgs[c]);
+        hipLaunchKernelGGL(rpdla::batch_set_cfg_kernel, dim3(1), dim3(64), 0, s, dc, rmax, zh,
+                           (DevCfg*)(base + w.cfg), (double*)(base + w.geo), c);
+    }
+    hipLaunchKernelGGL(rpdla::batch_reset_kernel, dim3(1), dim3(64), 0, s, A.ctl);
+    RPDLA_HIP(hipGetLastError());
+    const int64_t n_chunks = cdiv(atoms_per_cfg, atoms_per_chunk);
+    if (n_chunks == 0) return RPDLA_OK;
+    const bool mixed = precision == RPDLA_MIXED;
+    switch (cfgs[0].field) {
+    case 1: return mixed ? run_batched_impl<1, rpdla::ElecMixed>(A, n_chunks, s)
+                         : run_batched_impl<1, rpdla::ElecF64>(A, n_chunks, s);
+    case 3: return mixed ? run_batched_impl<3, rpdla::ElecMixed>(A, n_chunks, s)
+                         : run_batched_impl<3, rpdla::ElecF64>(A, n_chunks, s);
+    case 5: return mixed ? run_batched_impl<5, rpdla::ElecMixed>(A, n_chunks, s)
+                         : run_batched_impl<5, rpdla::ElecF64>(A, n_chunks, s);
+    case 10: return mixed ? run_batched_impl<10, rpdla::ElecMixed>(A, n_chunks, s)
+                          : run_batched_impl<10, rpdla::ElecF64>(A, n_chunks, s);
+    default: return mixed ? run_batched_impl<11, rpdla::ElecMixed>(A, n_chunks, s)
+                          : run_batched_impl<11, rpdla::ElecF64>(A, n_chunks, s);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,566 @@
+// rpdla_kernels.hpp -- HIP kernels for gfx950 (wave64): atom sampling,
+// ionization times, the Newton-Lorentz push (double and mixed precision) and
+// the energy-angle histogram.
+#pragma once
+
+#include "rpdla_device.hpp"
+
+namespace rpdla {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
+
+// ---------------------------------------------------------------------------
+// Atom sampling: one lane per atom, structure-of-arrays output.
+// r = R sqrt(u0), azimuth 2 pi u1, z = zh (2 u2 - 1)  (Sec. 2.1).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) sample_atoms_kernel(
+    uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n, double r_max, double z_half,
+    double* __restrict__ x, double* __restrict__ y, double* __restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const U64x4 r = philox4x64(first_atom + (uint64_t)i, 0, 0, 0, seed, (uint64_t)cfg);
+    const double rad = r_max * sqrt(u01(r.v[0]));
+    double sn, cs;
+    sincos(kTwoPi * u01(r.v[1]), &sn, &cs);
+    x[i] = rad * cs;
+    y[i] = rad * sn;
+    z[i] = z_half * (2.0 * u01(r.v[2]) - 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// Ionization.  One lane per atom.  Time axis in panels of width h from the
+// window start; state s (charge state k_first + s) accumulates GL-4 panel
+// integrals of its rate from the previous birth; at the panel where the sum
+// reaches the Exp(1) threshold the crossing is solved by bracketed Newton.
+// Panels where the rate bound proves w = 0 at every node (the rate is set to
+// exactly zero below lnw_zero) are skipped: before the first state's
+// possible window and after the current state's window.
+// ---------------------------------------------------------------------------
+template <int FIELD, class CFG>
+__device__ inline double emag2_f64(const CFG& c, double X, double Y, double Z, double tau)
+{
+    double ax, ay, az, bx, by, bz;
+    field_f64<FIELD, false, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
+    return ax * ax + ay * ay + az * az;
+}
+
+template <int FIELD, class CFG>
+__device__ inline double rate_at(const CFG& c, int s, double X, double Y, double Z, double tau)
+{
+    return adk_rate_n(c, s, emag2_f64<FIELD>(c, X, Y, Z, tau));
+}
+
+template <int FIELD, class CFG>
+__device__ inline double gl4_integral(const CFG& c, int s, double X, double Y, double Z,
+                                      double a, double b)
+{
+    const double h = 0.5 * (b - a), m = 0.5 * (a + b);
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc += c.gl_w[i] * rate_at<FIELD>(c, s, X, Y, Z, m + h * c.gl_x[i]);
+    return h * acc;
+}
+
+template <int FIELD, class CFG>
+__device__ double solve_crossing(const CFG& c, int s, double X, double Y, double Z, double lo,
+                                 double hi, double target, double Ghi)
+{
+    if (!(target > 0.0)) return lo;
+    double tl = lo, th = hi;
+    double t = lo + (hi - lo) * (target / Ghi);
+    if (!(t > tl && t < th)) t = 0.5 * (tl + th);
+    for (int it = 0; it < 100; ++it) {
+        const double gd = gl4_integral<FIELD>(c, s, X, Y, Z, lo, t) - target;
+        if (gd == 0.0) return t;
+        if (gd > 0.0) th = t; else tl = t;
+        const double tol = ldexp(fmax(fabs(t), kTwoPi), -40);
+        const double w = rate_at<FIELD>(c, s, X, Y, Z, t);
+        double tn = __builtin_nan("");
+        if (w > 0.0) {
+            const double dlt = gd / w;
+            if (fabs(dlt) <= tol) return t - dlt;
+            tn = t - dlt;
+        }
+        if (!(tn > tl && tn < th)) tn = 0.5 * (tl + th);
+        const double step = fabs(tn - t);
+        t = tn;
+        if (step <= tol) break;
+    }
+    return t;
+}
+
+// Panel range [j_lo, j_hi] outside which state s has w = 0 at every node.
+template <class CFG>
+__device__ inline bool state_window(const CFG& c, int s, double bound2, double Zc, double tau_s,
+                                    double h, int64_t M, int64_t& j_lo, int64_t& j_hi)
+{
+    const double thr = c.adk_a2thr[s];
+    if (!(bound2 >= thr)) return false;            // never reaches a nonzero rate
+    if (c.field == 11) { j_lo = 0; j_hi = M - 1; return true; }
+    const double smax = sqrt(0.5 * log(bound2 / thr));
+    const double half = smax / c.inv_T0n;          // in normalized time
+    const double lo = floor((Zc - half - tau_s) / h) - 1.0;
+    const double hi = ceil((Zc + half - tau_s) / h) + 1.0;
+    j_lo = lo < 0.0 ? 0 : (lo > (double)(M - 1) ? M - 1 : (int64_t)lo);
+    j_hi = hi > (double)(M - 1) ? M - 1 : (hi < 0.0 ? 0 : (int64_t)hi);
+    return true;
+}
+
+// Birth times of one atom (index `atom`, normalized position X, Y, Z) for
+// states k_first..k_first+K-1, written to out[0..K) in seconds.
+template <int FIELD, class CFG>
+__device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t atom, double X,
+                            double Y, double Z, int k_first, int K, double* __restrict__ out)
+{
+    for (int s = 0; s < K; ++s) out[s] = __builtin_inf();
+    const double tz = (c.window == 0) ? Z : 0.0;
+    const double tau_s = tz - c.tb_n, tau_e = tz + c.ta_n;
+    const double h = c.hn;
+    const int64_t M = (int64_t)ceil((tau_e - tau_s) / h);
+    const double b2 = bound2_f64<FIELD>(c, X, Y, Z);
+    const double Zc = Z;  // the envelope peaks at tau = Z for the pulse models
+
+    int s = 0;
+    double target = -log(uniform_j(seed, cfg, atom, k_first + 2));
+    // states with a zero threshold are born where they start
+    while (s < K && !(target > 0.0)) {
+        out[s] = tau_s * c.inv_omega;
+        ++s;
+        if (s < K) target = -log(uniform_j(seed, cfg, atom, k_first + s + 2));
+    }
+    if (s >= K) return;
+    int64_t j_lo, j_hi;
+    if (!state_window(c, k_first - 1 + s, b2, Zc, tau_s, h, M, j_lo, j_hi)) return;
+    double I = 0.0;
+    double tstart = tau_s;
+    for (int64_t j = j_lo; j < M; ++j) {
+        if (j > j_hi) break;
+        const double a = tau_s + (double)j * h;
+        const double b = (j == M - 1) ? tau_e : tau_s + (double)(j + 1) * h;
+        bool done = false;
+        while (true) {
+            const int ks = k_first - 1 + s;
+            const double lo = (tstart > a) ? tstart : a;
+            const double seg = gl4_integral<FIELD>(c, ks, X, Y, Z, lo, b);
+            if (I + seg < target) { I += seg; break; }
+            const double t = solve_crossing<FIELD>(c, ks, X, Y, Z, lo, b, target - I, seg);
+            out[s] = t * c.inv_omega;
+            ++s;
+            if (s >= K) { done = true; break; }
+            target = -log(uniform_j(seed, cfg, atom, k_first + s + 2));
+            I = 0.0;
+            tstart = t;
+            int64_t nlo, nhi;
+            if (!state_window(c, k_first - 1 + s, b2, Zc, tau_s, h, M, nlo, nhi)) {
+                if (!(target > 0.0)) { j_hi = M - 1; continue; }
+                done = true;
+                break;
+            }
+            j_hi = (target > 0.0) ? nhi : M - 1;
+        }
+        if (done) break;
+    }
+}
+
+template <int FIELD>
+__global__ void __launch_bounds__(256) ionize_kernel(
+    DevCfg c, uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n,
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    int k_first, int k_last, double* __restrict__ t_birth)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int K = k_last - k_first + 1;
+    ionize_atom<FIELD>(c, seed, cfg, first_atom + (uint64_t)i, x[i] * c.k, y[i] * c.k,
+                       z[i] * c.k, k_first, K, t_birth + i * K);
+}
+
+// ---------------------------------------------------------------------------
+// Push.  One electron per lane: state (X, u) advanced by classical RK4 with
+// fixed step h from its birth to the end of its atom's window (steps start at
+// tau0 + n h, the last one ends on the window end).
+// ---------------------------------------------------------------------------
+template <int FIELD, class CFG>
+__device__ inline void rhs_f64(const CFG& c, double tau, double X, double Y, double Z, double ux,
+                               double uy, double uz, double& dX, double& dY, double& dZ,
+                               double& dux, double& duy, double& duz)
+{
+    double ax, ay, az, bx, by, bz;
+    field_f64<FIELD, true, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
+    const double ig = rsqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    dX = ux * ig; dY = uy * ig; dZ = uz * ig;
+    dux = -(ax + dY * bz - dZ * by);
+    duy = -(ay + dZ * bx - dX * bz);
+    duz = -(az + dX * by - dY * bx);
+}
+
+struct ElecF64 {
+    double X, Y, Z, ux, uy, uz, tau0, taue;
+    int64_t n, N;
+};
+
+// Set up an electron born at rest at t0 [s] at atom position (x, y, z) [m].
+// Returns false (invalid slot) for a birth more than one step before the
+// window start, which also bounds the step count of every lane.
+template <class CFG>
+__device__ inline bool elec_init(const CFG& c, ElecF64& e, double t0, double x, double y, double z)
+{
+    e.X = x * c.k; e.Y = y * c.k; e.Z = z * c.k;
+    e.ux = e.uy = e.uz = 0.0;
+    e.tau0 = t0 * c.omega;
+    const double tz = (c.window == 0) ? e.Z : 0.0;
+    e.taue = tz + c.ta_n;
+    e.n = 0;
+    e.N = 0;
+    if (!(e.tau0 >= tz - c.tb_n - c.hn)) return false;
+    e.N = (int64_t)ceil((e.taue - e.tau0) / c.hn);
+    return true;
+}
+
+template <int FIELD, class CFG>
+__device__ inline void elec_step(const CFG& c, ElecF64& e)
+{
+    const double h = c.hn;
+    const double ta = e.tau0 + (double)e.n * h;
+    const double hs = (e.n == e.N - 1) ? (e.taue - ta) : h;
+    const double hh = 0.5 * hs;
+    double kX, kY, kZ, kx, ky, kz, aX, aY, aZ, ax, ay, az;
+    rhs_f64<FIELD>(c, ta, e.X, e.Y, e.Z, e.ux, e.uy, e.uz, kX, kY, kZ, kx, ky, kz);
+    aX = kX; aY = kY; aZ = kZ; ax = kx; ay = ky; az = kz;
+    rhs_f64<FIELD>(c, ta + hh, e.X + hh * kX, e.Y + hh * kY, e.Z + hh * kZ, e.ux + hh * kx,
+                   e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    aX += 2.0 * kX; aY += 2.0 * kY; aZ += 2.0 * kZ;
+    ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
+    rhs_f64<FIELD>(c, ta + hh, e.X + hh * kX, e.Y + hh * kY, e.Z + hh * kZ, e.ux + hh * kx,
+                   e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    aX += 2.0 * kX; aY += 2.0 * kY; aZ += 2.0 * kZ;
+    ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
+    rhs_f64<FIELD>(c, ta + hs, e.X + hs * kX, e.Y + hs * kY, e.Z + hs * kZ, e.ux + hs * kx,
+                   e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx, ky, kz);
+    const double w6 = hs / 6.0;
+    e.X += w6 * (aX + kX); e.Y += w6 * (aY + kY); e.Z += w6 * (aZ + kZ);
+    e.ux += w6 * (ax + kx); e.uy += w6 * (ay + ky); e.uz += w6 * (az + kz);
+    ++e.n;
+}
+
+template <class CFG>
+__device__ inline void elec_final(const CFG& c, const ElecF64& e, double& ux, double& uy,
+                                  double& uz, double& xf, double& yf, double& zf)
+{
+    ux = e.ux; uy = e.uy; uz = e.uz;
+    xf = e.X * c.inv_k; yf = e.Y * c.inv_k; zf = e.Z * c.inv_k;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: the field and the RK4 stage arithmetic in float; time,
+// position and the carrier phase in double.  The phase tau - Z is formed in
+// double and reduced to turns in [-1/2, 1/2] before the float sine/cosine
+// (the hardware sine/cosine take turns); the momentum is kept in float with
+// a Kahan compensation term.
+// ---------------------------------------------------------------------------
+template <int ORDER, class CFG>
+__device__ inline void rp_field_mixed(const CFG& c, double X, double Y, double Z, double tau,
+                                      float& ax, float& ay, float& az, float& bx, float& by)
+{
+    const double d = tau - Z;
+    double turns = d * kInvTwoPi;
+    turns -= rint(turns);
+    const float Xf = (float)X, Yf = (float)Y;
+    const float r2 = (Xf * Xf + Yf * Yf) * (float)c.inv_w0n2;
+    const float zeta = (float)(Z * c.inv_zrn);
+    const float iD = __builtin_amdgcn_rcpf(1.0f + zeta * zeta);
+    const float rD = r2 * iD;
+    const float ph = (float)turns + ((float)c.phi0 - rD * zeta) * (float)kInvTwoPi;
+    const float s = (float)(d * c.inv_T0n);
+    const float g = (float)c.a0 * __builtin_amdgcn_exp2f(-(rD + s * s) * 1.4426950408889634f);
+    const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+    Cx<float> Q[9];
+    rp_amplitudes<ORDER, float>(g, cs, sn, Cx<float>{iD, zeta * iD}, Q);
+    float PE, PB, EZ;
+    rp_combine<ORDER, float>(Q, r2, (float)c.eps, (float)c.e2, (float)c.e3, (float)c.e4, PE, PB,
+                             EZ);
+    const float pe = (float)c.er_scale * PE * (float)c.inv_w0n;
+    const float pb = PB * (float)c.inv_w0n;
+    ax = pe * Xf; ay = pe * Yf; az = (float)c.ez_scale * EZ;
+    bx = -pb * Yf; by = pb * Xf;
+}
+
+template <int FIELD, class CFG>
+__device__ inline void field_mixed(const CFG& c, double X, double Y, double Z, double tau,
+                                   float& ax, float& ay, float& az, float& bx, float& by,
+                                   float& bz)
+{
+    if constexpr (FIELD == 11) {
+        ax = (float)c.tE[0]; ay = (float)c.tE[1]; az = (float)c.tE[2];
+        bx = (float)c.tB[0]; by = (float)c.tB[1]; bz = (float)c.tB[2];
+    } else if constexpr (FIELD == 10) {
+        const double d = tau - Z;
+        double turns = (d + c.phi0) * kInvTwoPi;
+        turns -= rint(turns);
+        const float s = (float)(d * c.inv_T0n);
+        const float e = (float)c.a0 * __builtin_amdgcn_exp2f(-s * s * 1.4426950408889634f)
+                        * __builtin_amdgcn_cosf((float)turns);
+        ax = e; ay = 0.f; az = 0.f; bx = 0.f; by = e; bz = 0.f;
+    } else {
+        rp_field_mixed<FIELD, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by);
+        bz = 0.f;
+    }
+}
+
+template <int FIELD, class CFG>
+__device__ inline void rhs_mixed(const CFG& c, double tau, double X, double Y, double Z, float ux,
+                                 float uy, float uz, float& dX, float& dY, float& dZ, float& dux,
+                                 float& duy, float& duz)
+{
+    float ax, ay, az, bx, by, bz;
+    field_mixed<FIELD, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
+    const float ig = __builtin_amdgcn_rsqf(1.0f + ux * ux + uy * uy + uz * uz);
+    dX = ux * ig; dY = uy * ig; dZ = uz * ig;
+    dux = -(ax + dY * bz - dZ * by);
+    duy = -(ay + dZ * bx - dX * bz);
+    duz = -(az + dX * by - dY * bx);
+}
+
+__device__ inline void kahan_add(float& s, float& comp, float v)
+{
+    const float y = v - comp;
+    const float t = s + y;
+    comp = (t - s) - y;
+    s = t;
+}
+
+struct ElecMixed {
+    double X, Y, Z, tau0, taue;
+    float ux, uy, uz, cx, cy, cz;
+    int64_t n, N;
+};
+
+template <class CFG>
+__device__ inline bool elec_init(const CFG& c, ElecMixed& e, double t0, double x, double y, double z)
+{
+    e.X = x * c.k; e.Y = y * c.k; e.Z = z * c.k;
+    e.ux = e.uy = e.uz = 0.f; e.cx = e.cy = e.cz = 0.f;
+    e.tau0 = t0 * c.omega;
+    const double tz = (c.window == 0) ? e.Z : 0.0;
+    e.taue = tz + c.ta_n;
+    e.n = 0;
+    e.N = 0;
+    if (!(e.tau0 >= tz - c.tb_n - c.hn)) return false;
+    e.N = (int64_t)ceil((e.taue - e.tau0) / c.hn);
+    return true;
+}
+
+template <int FIELD, class CFG>
+__device__ inline void elec_step(const CFG& c, ElecMixed& e)
+{
+    const double h = c.hn;
+    const double ta = e.tau0 + (double)e.n * h;
+    const double hsd = (e.n == e.N - 1) ? (e.taue - ta) : h;
+    const float hs = (float)hsd, hh = 0.5f * hs;
+    const double hhd = 0.5 * hsd;
+    float kX, kY, kZ, kx, ky, kz, aX, aY, aZ, ax, ay, az;
+    rhs_mixed<FIELD>(c, ta, e.X, e.Y, e.Z, e.ux, e.uy, e.uz, kX, kY, kZ, kx, ky, kz);
+    aX = kX; aY = kY; aZ = kZ; ax = kx; ay = ky; az = kz;
+    rhs_mixed<FIELD>(c, ta + hhd, e.X + hhd * kX, e.Y + hhd * kY, e.Z + hhd * kZ, e.ux + hh * kx,
+                     e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    aX += 2.f * kX; aY += 2.f * kY; aZ += 2.f * kZ;
+    ax += 2.f * kx; ay += 2.f * ky; az += 2.f * kz;
+    rhs_mixed<FIELD>(c, ta + hhd, e.X + hhd * kX, e.Y + hhd * kY, e.Z + hhd * kZ, e.ux + hh * kx,
+                     e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    aX += 2.f * kX; aY += 2.f * kY; aZ += 2.f * kZ;
+    ax += 2.f * kx; ay += 2.f * ky; az += 2.f * kz;
+    rhs_mixed<FIELD>(c, ta + hsd, e.X + hsd * kX, e.Y + hsd * kY, e.Z + hsd * kZ, e.ux + hs * kx,
+                     e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx, ky, kz);
+    const double w6d = hsd / 6.0;
+    const float w6 = hs / 6.0f;
+    e.X += w6d * (double)(aX + kX); e.Y += w6d * (double)(aY + kY); e.Z += w6d * (double)(aZ + kZ);
+    kahan_add(e.ux, e.cx, w6 * (ax + kx));
+    kahan_add(e.uy, e.cy, w6 * (ay + ky));
+    kahan_add(e.uz, e.cz, w6 * (az + kz));
+    ++e.n;
+}
+
+template <class CFG>
+__device__ inline void elec_final(const CFG& c, const ElecMixed& e, double& ux, double& uy,
+                                  double& uz, double& xf, double& yf, double& zf)
+{
+    ux = (double)e.ux; uy = (double)e.uy; uz = (double)e.uz;
+    xf = e.X * c.inv_k; yf = e.Y * c.inv_k; zf = e.Z * c.inv_k;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent push over one configuration.  A lane whose electron has reached
+// its window end writes it out and takes the next slot from a global counter
+// (one atomic per wave per refill, ranks from the ballot), so lanes stay busy
+// however uneven the step counts are.  Unborn slots are written as NaN when
+// taken.
+// ---------------------------------------------------------------------------
+struct PushIO {
+    const double* tb; const double* x0; const double* y0; const double* z0;
+    int32_t spa; int64_t n_slots;
+    double* ux; double* uy; double* uz; double* xf; double* yf; double* zf;
+    unsigned long long* queue;
+};
+
+__device__ inline void write_nan(const PushIO& io, int64_t j)
+{
+    const double q = __builtin_nan("");
+    io.ux[j] = q; io.uy[j] = q; io.uz[j] = q; io.xf[j] = q; io.yf[j] = q; io.zf[j] = q;
+}
+
+// Wave-cooperative refill: lanes with need == true get consecutive queue
+// indices (called by every lane of the wave).
+__device__ inline int64_t queue_take(unsigned long long* queue, bool need)
+{
+    const uint64_t m = __ballot(need);
+    if (m == 0) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    return need ? (int64_t)(base + (unsigned long long)rank) : -1;
+}
+
+template <int FIELD, class ELEC>
+__global__ void __launch_bounds__(256) push_kernel(DevCfg c, PushIO io)
+{
+    int64_t idx = -1;
+    bool exhausted = false;
+    ELEC e;
+    e.n = e.N = 0;
+    while (true) {
+        // refill lanes without an electron (unborn slots are consumed here)
+        while (true) {
+            const bool need = (idx < 0) && !exhausted;
+            if (__ballot(need) == 0) break;
+            const int64_t j = queue_take(io.queue, need);
+            if (need) {
+                if (j >= io.n_slots) {
+                    exhausted = true;
+                } else {
+                    const double t0 = io.tb[j];
+                    if (!(t0 < __builtin_inf())) {
+                        write_nan(io, j);
+                    } else {
+                        const int64_t a = j / io.spa;
+                        if (!elec_init(c, e, t0, io.x0[a], io.y0[a], io.z0[a])) {
+                            write_nan(io, j);
+                            continue;
+                        }
+                        idx = j;
+                        if (e.N <= 0) {
+                            elec_final(c, e, io.ux[j], io.uy[j], io.uz[j], io.xf[j], io.yf[j],
+                                       io.zf[j]);
+                            idx = -1;
+                        }
+                    }
+                }
+            }
+        }
+        if (__ballot(idx >= 0) == 0) break;
+        if (idx >= 0) {
+            elec_step<FIELD>(c, e);
+            if (e.n == e.N) {
+                elec_final(c, e, io.ux[idx], io.uy[idx], io.uz[idx], io.xf[idx], io.yf[idx],
+                           io.zf[idx]);
+                idx = -1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Histogram.  Each lane computes its bin key; lanes of a wave that share a
+// key are merged (leader takes the key, ballot finds the matches, one atomic
+// per distinct key); the six tallies are ballot-counted per wave.
+// ---------------------------------------------------------------------------
+struct HistArgs {
+    int32_t nE, nA, angle;
+    double lo, width;
+    double mec2;  // electron rest energy [MeV]
+};
+
+// Bin key of one electron: >= 0 histogram cell index, or a negative tally code
+// -(tally+1) for tallies 2..5; dir returned separately (0 fwd, 1 bwd, -1 none).
+__device__ inline int64_t bin_key(const HistArgs& H, double tb, double ux, double uy, double uz,
+                                  int& tally, int& dir)
+{
+#pragma clang fp contract(off)
+    dir = -1;
+    if (!(tb < __builtin_inf())) { tally = 4; return -1; }
+    if (isnan(ux) || isnan(uy) || isnan(uz)) { tally = 5; return -1; }
+    const double up2 = ux * ux + uy * uy;
+    const double u2 = (ux * ux + uy * uy) + uz * uz;
+    const double K = H.mec2 * u2 / (sqrt(1.0 + u2) + 1.0);
+    dir = (uz > 0.0) ? 0 : 1;
+    const double fe = floor((log10(K) - H.lo) / H.width);
+    if (!(fe >= 0.0)) { tally = 2; return -1; }
+    if (fe >= (double)H.nE) { tally = 3; return -1; }
+    double fa;
+    const double pi = 3.14159265358979323846;
+    if (H.angle == 0) fa = floor(atan2(sqrt(up2), uz) / pi * (double)H.nA);
+    else fa = floor((atan2(uy, ux) + pi) / (2.0 * pi) * (double)H.nA);
+    int ia = (int)fa;
+    ia = ia > H.nA - 1 ? H.nA - 1 : (ia < 0 ? 0 : ia);
+    tally = -1;
+    return ((int64_t)dir * H.nE + (int64_t)fe) * H.nA + ia;
+}
+
+__device__ inline void wave_hist_commit(int64_t key, int tally, int dir,
+                                        unsigned long long* __restrict__ counts,
+                                        unsigned long long* __restrict__ tallies)
+{
+    const int lane = __lane_id();
+    // aggregate equal keys
+    bool pending = key >= 0;
+    while (true) {
+        const uint64_t act = __ballot(pending);
+        if (act == 0) break;
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const int64_t lk = __shfl(key, leader);
+        const uint64_t same = __ballot(pending && key == lk);
+        if (lane == leader) atomicAdd(&counts[lk], (unsigned long long)__popcll(same));
+        if (pending && key == lk) pending = false;
+    }
+    // tallies: 0 fwd, 1 bwd, 2 below, 3 above, 4 unborn, 5 NaN
+    const uint64_t t0 = __ballot(dir == 0), t1 = __ballot(dir == 1);
+    const uint64_t t2 = __ballot(tally == 2), t3 = __ballot(tally == 3);
+    const uint64_t t4 = __ballot(tally == 4), t5 = __ballot(tally == 5);
+    if (lane == 0) {
+        if (t0) atomicAdd(&tallies[0], (unsigned long long)__popcll(t0));
+        if (t1) atomicAdd(&tallies[1], (unsigned long long)__popcll(t1));
+        if (t2) atomicAdd(&tallies[2], (unsigned long long)__popcll(t2));
+        if (t3) atomicAdd(&tallies[3], (unsigned long long)__popcll(t3));
+        if (t4) atomicAdd(&tallies[4], (unsigned long long)__popcll(t4));
+        if (t5) atomicAdd(&tallies[5], (unsigned long long)__popcll(t5));
+    }
+}
+
+__global__ void __launch_bounds__(256) histogram_kernel(
+    HistArgs H, int64_t n, const double* __restrict__ tb, const double* __restrict__ ux,
+    const double* __restrict__ uy, const double* __restrict__ uz,
+    unsigned long long* __restrict__ counts, unsigned long long* __restrict__ tallies)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // wave-uniform trip count so every lane takes part in the ballots
+    const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t b = base0; b < n; b += stride) {
+        const int64_t i = b + __lane_id();
+        int64_t key = -1;
+        int tally = -1, dir = -1;
+        if (i < n) key = bin_key(H, tb[i], ux[i], uy[i], uz[i], tally, dir);
+        wave_hist_commit(key, tally, dir, counts, tallies);
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+}  // namespace rpdla
