@@ -494,7 +494,8 @@ void orc_push_one(const orc_laser* L, double t0, double t_end, double h,
 
 /* Push every born slot from rest (Sec. 2.1: electrons born with zero
  * momentum at their ionization time).  Slot s belongs to atom
- * s / slots_per_atom.  Unborn slots (t_birth = +INF) get NaN outputs. */
+ * s / slots_per_atom.  Unborn slots (t_birth = +INF) get NaN outputs, and so
+ * do births more than one step before the window start (invalid input). */
 void orc_push(const orc_laser* L, int64_t n_slots, const double* t_birth,
               const double* x0, const double* y0, const double* z0, int slots_per_atom,
               double* ux, double* uy, double* uz, double* xf, double* yf, double* zf)
@@ -509,6 +510,10 @@ void orc_push(const orc_laser* L, int64_t n_slots, const double* t_birth,
         }
         double ts, te;
         orc_window(L, z0[a], &ts, &te);
+        if (!(t0 >= ts - L->dt)) {   /* birth before the window: invalid slot */
+            ux[s] = uy[s] = uz[s] = xf[s] = yf[s] = zf[s] = NAN;
+            continue;
+        }
         double X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
         orc_push_one(L, t0, te, L->dt, X0, U0, XF, UF);
         ux[s] = UF[0]; uy[s] = UF[1]; uz[s] = UF[2];
