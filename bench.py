@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--atoms", type=int, default=None, help="override (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -97,6 +100,13 @@ def main():
     from paper_2509_01741_amd import pipeline, workloads
 
     torch.cuda.set_device(0)
+    if args.copy_ref_mib > 0:
+        src = torch.ones(args.copy_ref_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy reference: {args.copy_ref_mib} MiB read + written")
+        del src, dst
     wl = workloads.FULL_FP64
     ens = pipeline.Ensemble(wl, precision=B.RPDLA_FP64, n_atoms=args.atoms)
     log(f"workload {wl['name']}: {ens.n} atoms x {ens.K} states = {ens.n * ens.K} slots")

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rpdla_fastmath.hpp"
+
 namespace rpdla {
 
 constexpr int kMaxStates = 10;
@@ -175,14 +177,14 @@ __device__ inline void rp_field_f64(const CFG& c, double X, double Y, double Z, 
 {
     const double r2 = (X * X + Y * Y) * c.inv_w0n2;
     const double zeta = Z * c.inv_zrn;
-    const double iD = 1.0 / (1.0 + zeta * zeta);
+    const double iD = fm::rcp_f64(1.0 + zeta * zeta);
     const double rD = r2 * iD;
     const double d = tau - Z;
     const double Psi = c.phi0 + d - rD * zeta;
     const double s = d * c.inv_T0n;
-    const double g = c.a0 * exp(-rD - s * s);
+    const double g = c.a0 * fm::exp_f64(-rD - s * s);
     double sn, cs;
-    sincos(Psi, &sn, &cs);
+    fm::sincos_f64(Psi, &sn, &cs);
     Cx<double> Q[9];
     rp_amplitudes<ORDER, double>(g, cs, sn, Cx<double>{iD, zeta * iD}, Q);
     double PE, PB, EZ;
@@ -236,7 +238,9 @@ __device__ inline void field_f64(const CFG& c, double X, double Y, double Z, dou
     } else if constexpr (FIELD == 10) {  // plane wave, x polarized
         const double d = tau - Z;
         const double s = d * c.inv_T0n;
-        const double e = c.a0 * exp(-s * s) * cos(d + c.phi0);
+        double sn, cs;
+        fm::sincos_f64(d + c.phi0, &sn, &cs);
+        const double e = c.a0 * fm::exp_f64(-s * s) * cs;
         ax = e; ay = 0.0; az = 0.0;
         bx = 0.0; by = e; bz = 0.0;
     } else {
@@ -267,7 +271,7 @@ __device__ inline double adk_rate_n(const CFG& c, int s, double a2)
     if (!(a2 > 0.0)) return 0.0;
     const double l = c.adk_c0[s] - c.adk_c1h[s] * log(a2) - c.adk_c2[s] * rsqrt(a2);
     if (l < c.lnw_zero) return 0.0;
-    return exp(l);
+    return fm::exp_f64(l);
 }
 
 }  // namespace rpdla

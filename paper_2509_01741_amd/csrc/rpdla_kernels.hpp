@@ -239,7 +239,7 @@ __device__ inline void elec_step(const CFG& c, ElecF64& e)
     ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
     rhs_f64<FIELD>(c, ta + hs, e.X + hs * kX, e.Y + hs * kY, e.Z + hs * kZ, e.ux + hs * kx,
                    e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx, ky, kz);
-    const double w6 = hs / 6.0;
+    const double w6 = hs * (1.0 / 6.0);
     e.X += w6 * (aX + kX); e.Y += w6 * (aY + kY); e.Z += w6 * (aZ + kZ);
     e.ux += w6 * (ax + kx); e.uy += w6 * (ay + ky); e.uz += w6 * (az + kz);
     ++e.n;

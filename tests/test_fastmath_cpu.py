@@ -1,0 +1,99 @@
+"""The double-precision sine/cosine, exponential and reciprocal used by the
+GPU kernels (csrc/rpdla_fastmath.hpp), compiled for the host with g++ from
+the same header, against libm and mpmath, and the generated coefficient
+table against a fresh run of its generator."""
+import ctypes as C
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2509_01741_amd", "csrc")
+
+HARNESS = r'''
+#include "rpdla_fastmath.hpp"
+extern "C" void fm_sincos(long n, const double* x, double* s, double* c) {
+    for (long i = 0; i < n; ++i) rpdla::fm::sincos_f64(x[i], s + i, c + i);
+}
+extern "C" void fm_exp(long n, const double* x, double* y) {
+    for (long i = 0; i < n; ++i) y[i] = rpdla::fm::exp_f64(x[i]);
+}
+extern "C" void fm_rcp(long n, const double* x, double* y) {
+    for (long i = 0; i < n; ++i) y[i] = rpdla::fm::rcp_f64(x[i]);
+}
+'''
+
+
+@pytest.fixture(scope="module")
+def fm(tmp_path_factory):
+    d = tmp_path_factory.mktemp("fm")
+    src = d / "h.cpp"
+    src.write_text(HARNESS)
+    so = d / "libfm.so"
+    subprocess.run(["g++", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-I" + CSRC,
+                    "-o", str(so), str(src)], check=True)
+    lib = C.CDLL(str(so))
+    P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+    lib.fm_sincos.argtypes = [C.c_long, P, P, P]
+    lib.fm_exp.argtypes = [C.c_long, P, P]
+    lib.fm_rcp.argtypes = [C.c_long, P, P]
+    return lib
+
+
+def test_sincos_against_libm(fm):
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.uniform(-1e4, 1e4, 400000), rng.uniform(-4, 4, 100000),
+                        np.arange(-64, 65) * np.pi / 4, [0.0, -0.0, 1e-300, 2.0**-30]])
+    s = np.zeros_like(x); c = np.zeros_like(x)
+    fm.fm_sincos(x.size, x, s, c)
+    # absolute error in units of 2^-53 (the functions are bounded by 1)
+    es = np.abs(s - np.sin(x)) / 2.0**-53
+    ec = np.abs(c - np.cos(x)) / 2.0**-53
+    assert es.max() <= 4 and ec.max() <= 4, (es.max(), ec.max())
+    assert np.all(s[-4:] == np.sin(x[-4:])) or np.max(np.abs(s[-4:] - x[-4:])) < 1e-300
+
+
+def test_sincos_against_mpmath(fm):
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.uniform(-3000, 3000, 300), rng.uniform(-1, 1, 100)])
+    s = np.zeros_like(x); c = np.zeros_like(x)
+    fm.fm_sincos(x.size, x, s, c)
+    for xi, si, ci in zip(x, s, c):
+        xs = mp.mpf(xi)
+        assert abs(si - mp.sin(xs)) <= 2 * 2.0**-53
+        assert abs(ci - mp.cos(xs)) <= 2 * 2.0**-53
+
+
+def test_exp_against_libm(fm):
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.uniform(-745, 5, 400000), rng.uniform(-1, 1, 100000),
+                        [0.0, -1e-300, -708.0, -745.0, -746.0, -1e6]])
+    y = np.zeros_like(x)
+    fm.fm_exp(x.size, x, y)
+    ref = np.exp(x)
+    norm = ref > 2.2250738585072014e-308
+    rel = np.abs(y[norm] - ref[norm]) / ref[norm]
+    assert rel.max() <= 3 * 2.0**-53, rel.max()
+    assert np.all(np.abs(y[~norm] - ref[~norm]) <= 4.9e-324 * 4)
+    assert fm and y[-6] == 1.0 and y[-1] == 0.0 and y[-2] == 0.0
+
+
+def test_rcp(fm):
+    rng = np.random.default_rng(4)
+    x = 1.0 + rng.uniform(0, 50, 100000) ** 2
+    y = np.zeros_like(x)
+    fm.fm_rcp(x.size, x, y)
+    rel = np.abs(y - 1.0 / x) * x
+    assert rel.max() <= 2 * 2.0**-53
+
+
+def test_coefficients_are_the_generator_output():
+    pytest.importorskip("mpmath")
+    out = subprocess.run([sys.executable, os.path.join(CSRC, "gen_fastmath.py")],
+                         capture_output=True, text=True, check=True).stdout
+    assert out.strip() == open(os.path.join(CSRC, "rpdla_fastmath_coeffs.hpp")).read().strip()
