@@ -25,11 +25,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 C_LIGHT = 299792458.0
-# FP64 operations per electron-step of the order-5 push (mul, add = 1, fma = 2;
-# special functions at the cost of their standard polynomial implementations).
-ALGO_FLOP_PER_STEP = 1041.0
+# FP64 floating-point operations of one RK4 step of one electron with the
+# order-5 field (mul, add = 1 FLOP, fma = 2; the sine/cosine, exponential,
+# reciprocal and reciprocal square root counted at the operations of their
+# polynomial implementations): 4 x (223 field + 27 Lorentz) + 85 RK4 = 1085.
+ALGO_FLOP_PER_STEP = 1085.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 PROFILE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_fp64_rp_ne_fp64_1m_traffic.json")
+KERNEL_SOURCES = ["rpdla_api.hip", "rpdla_device.hpp", "rpdla_kernels.hpp", "rpdla_batched.hpp",
+                  "rpdla_fastmath.hpp", "rpdla_fastmath_coeffs.hpp"]
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources: measured traffic is reported only for the
+    kernel build it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_01741_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -154,7 +169,8 @@ def main():
     if os.path.exists(PROFILE_TRAFFIC_FILE):
         try:
             tr = json.load(open(PROFILE_TRAFFIC_FILE))
-            traffic = tr.get("bytes_per_launch")
+            if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("atoms") == ens.n:
+                traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
 
