@@ -90,6 +90,43 @@ def cpu_baseline(ens, budget_s=15.0):
                        f"{t2:.1f} s) with the GPU's birth times; order-5 field, same laser")
 
 
+def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk):
+    """One timed batched sweep (after an untimed one that captures the graph)
+    on a side stream; electron-steps counted by the library."""
+    import torch
+    from paper_2509_01741_amd import binding as B
+    from paper_2509_01741_amd import pipeline
+    n_cfg = len(wl["lasers"])
+    spec = pipeline.hist_spec(wl["hist"])
+    dev = torch.device("cuda")
+    counts = torch.zeros((n_cfg, 2, spec.nE, spec.nA), dtype=torch.int64, device=dev)
+    tallies = torch.zeros((n_cfg, B.RPDLA_NTALLY), dtype=torch.int64, device=dev)
+    steps = torch.zeros(n_cfg, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, wl["k_first"],
+                                                     wl["k_last"]), dtype=torch.uint8, device=dev)
+    st = torch.cuda.Stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(st):
+        pipeline.run_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk, stream=st, workspace=ws,
+                           counts=counts, tallies=tallies, electron_steps=steps)
+        counts.zero_(); tallies.zero_(); steps.zero_()
+        a, b = ev(), ev()
+        a.record(st)
+        pipeline.run_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk, stream=st, workspace=ws,
+                           counts=counts, tallies=tallies, electron_steps=steps)
+        b.record(st)
+    st.synchronize()
+    ms = a.elapsed_time(b)
+    n_steps = int(steps.sum().item())
+    tal = tallies.sum(0).cpu().tolist()
+    bwd = tallies[:, 1].double() / (tallies[:, 0] + tallies[:, 1]).clamp(min=1).double()
+    return dict(workload=wl["name"], precision="mixed" if precision == B.RPDLA_MIXED else "f64",
+                configs=n_cfg, atoms_per_cfg=atoms_per_cfg, atoms_per_chunk=atoms_per_chunk,
+                chunks=-(-atoms_per_cfg // atoms_per_chunk), ms=round(ms, 2),
+                electron_steps=n_steps, electron_steps_per_s=n_steps / (ms * 1e-3),
+                born=int(tal[0] + tal[1]), backward_fraction_min_max=[float(bwd.min()), float(bwd.max())])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +135,7 @@ def main():
     ap.add_argument("--atoms", type=int, default=None, help="override (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -206,6 +244,19 @@ def main():
         )
         log(f"mixed: {mixed}")
 
+    batched = None
+    if not args.no_batched:
+        batched = {}
+        r = measure_sweep(workloads.SWEEP_FP64, B.RPDLA_FP64, 16384, 16384)
+        log(f"batched sweep FP64: {r}")
+        batched["sweep64_fp64"] = r
+        r = measure_sweep(workloads.SWEEP_FP64, B.RPDLA_MIXED, 16384, 16384)
+        log(f"batched sweep mixed: {r}")
+        batched["sweep64_mixed"] = r
+        r = measure_sweep(workloads.LARGE_MIXED, B.RPDLA_MIXED, 100_000, 50_000)
+        log(f"large mixed sweep: {r}")
+        batched["large16_mixed"] = r
+
     base = None
     if not args.no_cpu_baseline:
         try:
@@ -245,6 +296,7 @@ def main():
         "ionize_ms": round(ion_avg, 2),
         "tallies": dict(zip(["fwd", "bwd", "below", "above", "unborn", "nan"], tal)),
         "mixed": mixed,
+        "batched": batched,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

@@ -197,10 +197,13 @@ rpdla_status rpdla_histogram(int64_t n_slots, const double* t_birth, const doubl
  * configuration; each chunk runs sample -> ionize -> push -> histogram, the
  * push as ONE persistent launch over every configuration's electrons (one
  * global work queue, lanes refilled as their electron finishes; the
- * configuration table staged in LDS), the push epilogue binned directly.
+ * configuration table staged in LDS).
  * The chunk's launch sequence is captured once in a hipGraph and replayed.
  * counts: device uint64[n_cfg][2][nE][nA], tallies: device uint64[n_cfg][6],
- * accumulated.  workspace: device memory of at least
+ * accumulated; electron_steps: device uint64[n_cfg] (accumulated) receiving
+ * the number of RK4 steps taken per configuration, or NULL.  The chunk's
+ * final momenta are binned by a separate wave-merged histogram pass.
+ * workspace: device memory of at least
  * rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last)
  * bytes, 256-byte aligned, owned by the caller, not touched by other work
  * until the stream reaches the end of this call.
@@ -213,8 +216,8 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
                                uint32_t cfg_base, int64_t atoms_per_cfg, int64_t atoms_per_chunk,
                                double r_factor, int32_t k_first, int32_t k_last,
                                int32_t precision, const rpdla_hist_spec* spec,
-                               uint64_t* counts, uint64_t* tallies, void* workspace,
-                               size_t ws_bytes, void* stream);
+                               uint64_t* counts, uint64_t* tallies, uint64_t* electron_steps,
+                               void* workspace, size_t ws_bytes, void* stream);
 
 /* Status text and the calling thread's last error detail (never NULL). */
 const char* rpdla_status_string(rpdla_status s);

@@ -73,7 +73,7 @@ def _load():
         "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
         "rpdla_batched_workspace_bytes": (C.c_size_t, [i32, i64, i32, i32]),
         "rpdla_run_batched": (i32, [LP, i32, u64, u32, i64, i64, d, i32, i32, i32, HP, vp, vp,
-                                    vp, C.c_size_t, vp]),
+                                    vp, vp, C.c_size_t, vp]),
         "rpdla_status_string": (C.c_char_p, [i32]),
         "rpdla_last_error": (C.c_char_p, []),
         "rpdla_version": (C.c_char_p, []),
@@ -196,7 +196,9 @@ def rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last) -> in
 
 def rpdla_run_batched(lasers, seed, cfg_base, atoms_per_cfg, atoms_per_chunk, r_factor, k_first,
                       k_last, precision, spec: rpdla_hist_spec, counts=None, tallies=None,
-                      workspace=None, stream=None, device=None):
+                      workspace=None, stream=None, device=None, electron_steps=None):
+    """Returns (counts [n_cfg, 2, nE, nA], tallies [n_cfg, 6]); electron_steps,
+    if given, is an int64 tensor [n_cfg] that accumulates the RK4 steps."""
     n_cfg = len(lasers)
     arr = (rpdla_laser * n_cfg)(*lasers)
     nb = 2 * spec.nE * spec.nA
@@ -212,6 +214,8 @@ def rpdla_run_batched(lasers, seed, cfg_base, atoms_per_cfg, atoms_per_chunk, r_
                                  r_factor, k_first, k_last, precision, C.byref(spec),
                                  _dev(counts, "counts", n_cfg * nb, torch.int64),
                                  _dev(tallies, "tallies", n_cfg * RPDLA_NTALLY, torch.int64),
+                                 (C.c_void_p(0) if electron_steps is None else
+                                  _dev(electron_steps, "electron_steps", n_cfg, torch.int64)),
                                  _dev(workspace, "workspace", need, torch.uint8),
                                  C.c_size_t(workspace.numel()), _stream(stream)),
            "rpdla_run_batched")

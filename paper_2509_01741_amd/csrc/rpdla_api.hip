@@ -373,7 +373,7 @@ namespace {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t cfg, geo, ctl, x, y, z, tb, total;
+    size_t cfg, geo, ctl, x, y, z, tb, ux, uy, uz, total;
 };
 
 WsLayout ws_layout(int n_cfg, int64_t apc, int K)
@@ -388,6 +388,9 @@ WsLayout ws_layout(int n_cfg, int64_t apc, int K)
     w.y = off; off += align256(na * sizeof(double));
     w.z = off; off += align256(na * sizeof(double));
     w.tb = off; off += align256(na * (size_t)K * sizeof(double));
+    w.ux = off; off += align256(na * (size_t)K * sizeof(double));
+    w.uy = off; off += align256(na * (size_t)K * sizeof(double));
+    w.uz = off; off += align256(na * (size_t)K * sizeof(double));
     w.total = off;
     return w;
 }
@@ -399,7 +402,7 @@ template <int FIELD, class ELEC>
 rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipStream_t s)
 {
     const size_t lds_i = (size_t)A.n_cfg * sizeof(DevCfg);
-    const size_t lds_p = (size_t)A.n_cfg * (sizeof(rpdla::PushCfg) + 6 * sizeof(unsigned long long));
+    const size_t lds_p = (size_t)A.n_cfg * (sizeof(rpdla::PushCfg) + sizeof(unsigned long long));
     auto* kpush = rpdla::batch_push_kernel<FIELD, ELEC>;
     auto* kion = rpdla::batch_ionize_kernel<FIELD>;
     int dev = 0, cus = 0, per_cu = 0;
@@ -411,12 +414,15 @@ rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipSt
     int64_t grid_p = (int64_t)cus * per_cu;
     if (cdiv(slots, 256) < grid_p) grid_p = cdiv(slots, 256);
     const unsigned grid_a = (unsigned)cdiv((int64_t)A.n_cfg * A.apc, 256);
+    int64_t grid_h = cdiv(slots, 256);
+    if (grid_h > 8192) grid_h = 8192;
 
     auto enqueue_chunk = [&](hipStream_t st) -> rpdla_status {
         hipLaunchKernelGGL(rpdla::batch_zero_queue_kernel, dim3(1), dim3(64), 0, st, A.ctl);
         hipLaunchKernelGGL(rpdla::batch_sample_kernel, dim3(grid_a), dim3(256), 0, st, A);
         hipLaunchKernelGGL(kion, dim3(grid_a), dim3(256), lds_i, st, A);
         hipLaunchKernelGGL(kpush, dim3((unsigned)grid_p), dim3(256), lds_p, st, A);
+        hipLaunchKernelGGL(rpdla::batch_hist_kernel, dim3((unsigned)grid_h), dim3(256), 0, st, A);
         hipLaunchKernelGGL(rpdla::batch_advance_kernel, dim3(1), dim3(64), 0, st, A.ctl);
         RPDLA_HIP(hipGetLastError());
         return RPDLA_OK;
@@ -476,7 +482,8 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
                                uint32_t cfg_base, int64_t atoms_per_cfg, int64_t atoms_per_chunk,
                                double r_factor, int32_t k_first, int32_t k_last, int32_t precision,
                                const rpdla_hist_spec* spec, uint64_t* counts, uint64_t* tallies,
-                               void* workspace, size_t ws_bytes, void* stream)
+                               uint64_t* electron_steps, void* workspace, size_t ws_bytes,
+                               void* stream)
 {
     if (!cfgs) return fail(RPDLA_EINVAL, "cfgs is NULL");
     if (n_cfg < 1) return fail(RPDLA_EINVAL, "n_cfg must be >= 1");
@@ -524,6 +531,7 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
     A.K = K;
     A.x = (double*)(base + w.x); A.y = (double*)(base + w.y); A.z = (double*)(base + w.z);
     A.tb = (double*)(base + w.tb);
+    A.ux = (double*)(base + w.ux); A.uy = (double*)(base + w.uy); A.uz = (double*)(base + w.uz);
     A.ctl = (rpdla::BatchCtl*)(base + w.ctl);
     A.H.nE = spec->nE; A.H.nA = spec->nA; A.H.angle = spec->angle;
     A.H.lo = spec->logE_min_MeV;
@@ -531,6 +539,7 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
     A.H.mec2 = kMeC2MeV;
     A.counts = (unsigned long long*)counts;
     A.tallies = (unsigned long long*)tallies;
+    A.steps = (unsigned long long*)electron_steps;
     // configuration table: written by tiny kernels (arguments copied at launch)
     for (int c = 0; c < n_cfg; ++c) {
         const DevCfg dc = make_cfg(&cfgs[c]);

@@ -2,17 +2,20 @@
 // and ionization over every configuration's atoms, then ONE persistent push
 // launch over every configuration's electrons with a single global work
 // queue (lanes refilled as their electron finishes, so uneven step counts
-// across wavelengths and powers balance themselves), the configuration table
-// staged in LDS and the energy-angle binning fused into the push epilogue.
+// across wavelengths and powers balance themselves) and the configuration
+// table staged in LDS, then one binning pass over the chunk's final momenta
+// into per-configuration energy-angle histograms.
 #pragma once
 
 #include "rpdla_kernels.hpp"
 
 namespace rpdla {
 
+constexpr int kMaxCfg = 64;
+
 struct BatchCtl {
-    unsigned long long chunk;  // index of the chunk being processed
-    unsigned long long queue;  // push work counter of the current chunk
+    unsigned long long chunk;            // index of the chunk being processed
+    unsigned long long queue[kMaxCfg];   // per-configuration push work counters
 };
 
 struct BatchArgs {
@@ -25,10 +28,12 @@ struct BatchArgs {
     int32_t k_first, K;
     double* x; double* y; double* z;  // [n_cfg * apc]
     double* tb;                       // [n_cfg * apc * K]
+    double* ux; double* uy; double* uz;  // final momenta [n_cfg * apc * K]
     BatchCtl* ctl;
     HistArgs H;
     unsigned long long* counts;       // [n_cfg][2 nE nA]
     unsigned long long* tallies;      // [n_cfg][6]
+    unsigned long long* steps;        // [n_cfg] electron-steps taken, or null
 };
 
 __global__ void batch_set_cfg_kernel(DevCfg c, double r_max, double z_half, DevCfg* table,
@@ -43,12 +48,15 @@ __global__ void batch_set_cfg_kernel(DevCfg c, double r_max, double z_half, DevC
 
 __global__ void batch_reset_kernel(BatchCtl* ctl)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) { ctl->chunk = 0ull; ctl->queue = 0ull; }
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) ctl->chunk = 0ull;
+        if (threadIdx.x < kMaxCfg) ctl->queue[threadIdx.x] = 0ull;
+    }
 }
 
 __global__ void batch_zero_queue_kernel(BatchCtl* ctl)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->queue = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x < kMaxCfg) ctl->queue[threadIdx.x] = 0ull;
 }
 
 __global__ void batch_advance_kernel(BatchCtl* ctl)
@@ -96,90 +104,145 @@ __global__ void __launch_bounds__(256) batch_ionize_kernel(BatchArgs A)
                        A.y[i] * cf.k, A.z[i] * cf.k, A.k_first, A.K, A.tb + i * A.K);
 }
 
+// Copy a wave-uniform record (same address in every lane) into scalar
+// registers: every 32-bit word goes through readfirstlane.
+template <class T>
+__device__ inline T uniform_copy(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "record must be a whole number of words");
+    T out;
+    const int* src = reinterpret_cast<const int*>(p);
+    int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return out;
+}
+
 // One persistent launch over n_cfg * apc * K slots.  Slot j belongs to
-// configuration j / (apc K) and atom (j / K) % apc of the chunk.
+// configuration j / (apc K) and atom (j / K) % apc of the chunk.  Every
+// configuration has its own work counter, and a wave works on ONE
+// configuration at a time: it starts on configuration (wave id mod n_cfg),
+// refills its lanes from that configuration's counter, and when the counter
+// is exhausted lets its lanes finish and moves on to the next configuration
+// that still has work.  The wave's configuration is therefore uniform: its
+// constants are copied from the LDS table into scalar registers once per
+// switch, and the step's vector registers hold electron state only.  Final
+// momenta go to the chunk's u arrays (NaN for invalid births; unborn and
+// inactive slots are not written).
 template <int FIELD, class ELEC>
-__global__ void __launch_bounds__(256) batch_push_kernel(BatchArgs A)
+__global__ void __launch_bounds__(256, 4) batch_push_kernel(BatchArgs A)
 {
     extern __shared__ double lds_raw[];
     const int ncfg = A.n_cfg;
     PushCfg* s_pc = reinterpret_cast<PushCfg*>(lds_raw);
-    unsigned long long* s_tal = reinterpret_cast<unsigned long long*>(s_pc + ncfg);
-    for (int w = threadIdx.x; w < ncfg; w += blockDim.x) s_pc[w] = push_cfg_of(A.cfgs[w]);
-    for (int w = threadIdx.x; w < ncfg * 6; w += blockDim.x) s_tal[w] = 0ull;
+    unsigned long long* s_steps = reinterpret_cast<unsigned long long*>(s_pc + ncfg);
+    for (int w = threadIdx.x; w < ncfg; w += blockDim.x) {
+        s_pc[w] = push_cfg_of(A.cfgs[w]);
+        s_steps[w] = 0ull;
+    }
     __syncthreads();
 
     const int64_t per_cfg = A.apc * A.K;
-    const int64_t n_slots = (int64_t)ncfg * per_cfg;
     const int64_t first = (int64_t)A.ctl->chunk * A.apc;
-    const int64_t nbins = 2ll * A.H.nE * A.H.nA;
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    int cw = __builtin_amdgcn_readfirstlane(wave % ncfg);
+    PushCfg uc = uniform_copy(&s_pc[cw]);
     int64_t idx = -1;
-    int ci = 0;
-    bool exhausted = false;
+    bool draining = false;
     ELEC e;
     e.n = e.N = 0;
     while (true) {
-        while (true) {
-            const bool need = (idx < 0) && !exhausted;
-            if (__ballot(need) == 0) break;
-            const int64_t j = queue_take(&A.ctl->queue, need);
-            if (need) {
-                if (j >= n_slots) {
-                    exhausted = true;
-                } else {
-                    const int c = (int)(j / per_cfg);
-                    const int64_t a = (j - (int64_t)c * per_cfg) / A.K;
-                    if (first + a < A.atoms_per_cfg) {
-                        const double t0 = A.tb[j];
-                        if (!(t0 < __builtin_inf())) {
-                            atomicAdd(&s_tal[c * 6 + 4], 1ull);
-                        } else {
-                            const int64_t ia = (int64_t)c * A.apc + a;
-                            if (elec_init(s_pc[c], e, t0, A.x[ia], A.y[ia], A.z[ia])) {
-                                ci = c;
-                                idx = j;
+        if (!draining) {
+            while (true) {
+                const bool need = idx < 0;
+                if (__ballot(need) == 0) break;
+                const int64_t j = queue_take(&A.ctl->queue[cw], need);
+                bool dry = false;
+                if (need) {
+                    if (j >= per_cfg) {
+                        dry = true;
+                    } else {
+                        const int64_t a = j / A.K;
+                        const int64_t js = (int64_t)cw * per_cfg + j;
+                        const double t0 = A.tb[js];
+                        if (first + a < A.atoms_per_cfg && t0 < __builtin_inf()) {
+                            const int64_t ia = (int64_t)cw * A.apc + a;
+                            if (elec_init(uc, e, t0, A.x[ia], A.y[ia], A.z[ia])) {
+                                idx = js;
+                                if (e.N > 0) atomicAdd(&s_steps[cw], (unsigned long long)e.N);
                             } else {
-                                atomicAdd(&s_tal[c * 6 + 5], 1ull);
+                                const double q = __builtin_nan("");
+                                A.ux[js] = q; A.uy[js] = q; A.uz[js] = q;
                             }
                         }
                     }
                 }
+                if (__ballot(dry) != 0) { draining = true; break; }
             }
         }
-        if (__ballot(idx >= 0) == 0) break;
-        bool finished = false;
-        if (idx >= 0) {
-            if (e.n < e.N) elec_step<FIELD>(s_pc[ci], e);
-            finished = (e.n >= e.N);
+        if (__ballot(idx >= 0) == 0) {
+            if (!draining) continue;
+            // this configuration is exhausted: move to the next one with work
+            int next = -1;
+            for (int k = 1; k <= ncfg && next < 0; ++k) {
+                const int c2 = (cw + k) % ncfg;
+                const unsigned long long taken = atomicAdd(&A.ctl->queue[c2], 0ull);
+                if ((int64_t)taken < per_cfg) next = c2;
+            }
+            if (next < 0) break;
+            cw = __builtin_amdgcn_readfirstlane(next);
+            uc = uniform_copy(&s_pc[cw]);
+            draining = false;
+            continue;
         }
-        if (__ballot(finished) != 0) {
-            int64_t key = -1;
-            int tally = -1, dir = -1;
-            if (finished) {
-                double ux, uy, uz, xf, yf, zf;
-                elec_final(s_pc[ci], e, ux, uy, uz, xf, yf, zf);
-                key = bin_key(A.H, 0.0, ux, uy, uz, tally, dir);
-                if (key >= 0) key += (int64_t)ci * nbins;
-                if (dir >= 0) atomicAdd(&s_tal[ci * 6 + dir], 1ull);
-                if (tally >= 2) atomicAdd(&s_tal[ci * 6 + tally], 1ull);
-                idx = -1;
-            }
-            // merge equal bins across the wave, one global atomic per bin
-            bool pending = key >= 0;
-            while (true) {
-                const uint64_t act = __ballot(pending);
-                if (act == 0) break;
-                const int leader = __ffsll((unsigned long long)act) - 1;
-                const int64_t lk = __shfl(key, leader);
-                const uint64_t same = __ballot(pending && key == lk);
-                if (__lane_id() == leader) atomicAdd(&A.counts[lk], (unsigned long long)__popcll(same));
-                if (pending && key == lk) pending = false;
-            }
+        if ((idx >= 0) && (e.n < e.N)) elec_step<FIELD>(uc, e);
+        if ((idx >= 0) && (e.n >= e.N)) {
+            double ux, uy, uz, xf, yf, zf;
+            elec_final(uc, e, ux, uy, uz, xf, yf, zf);
+            A.ux[idx] = ux; A.uy[idx] = uy; A.uz[idx] = uz;
+            idx = -1;
         }
     }
-    __syncthreads();
-    for (int w = threadIdx.x; w < ncfg * 6; w += blockDim.x)
-        if (s_tal[w]) atomicAdd(&A.tallies[w], s_tal[w]);
+    if (A.steps) {
+        __syncthreads();
+        for (int w = threadIdx.x; w < ncfg; w += blockDim.x)
+            if (s_steps[w]) atomicAdd(&A.steps[w], s_steps[w]);
+    }
+}
+
+// Bin the chunk's electrons into their configuration's histogram: one lane
+// per slot; bins and tallies merged across the wave (one atomic per distinct
+// key).  Tallies as in rpdla_histogram; inactive atoms of a partial chunk are
+// skipped.
+__global__ void __launch_bounds__(256) batch_hist_kernel(BatchArgs A)
+{
+    const int64_t per_cfg = A.apc * A.K;
+    const int64_t n_slots = (int64_t)A.n_cfg * per_cfg;
+    const int64_t first = (int64_t)A.ctl->chunk * A.apc;
+    const int64_t nbins = 2ll * A.H.nE * A.H.nA;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t b = base0; b < n_slots; b += stride) {
+        const int64_t j = b + __lane_id();
+        int64_t key = -1, tkey = -1, dkey = -1;
+        if (j < n_slots) {
+            const int c = (int)(j / per_cfg);
+            const int64_t a = (j - (int64_t)c * per_cfg) / A.K;
+            if (first + a < A.atoms_per_cfg) {
+                int tally = -1, dir = -1;
+                const double t0 = A.tb[j];
+                const bool born = t0 < __builtin_inf();
+                key = bin_key(A.H, t0, born ? A.ux[j] : 0.0, born ? A.uy[j] : 0.0,
+                              born ? A.uz[j] : 0.0, tally, dir);
+                if (key >= 0) key += (int64_t)c * nbins;
+                if (tally >= 2) tkey = (int64_t)c * 6 + tally;
+                if (dir >= 0) dkey = (int64_t)c * 6 + dir;
+            }
+        }
+        wave_merge_add(key, A.counts);
+        wave_merge_add(tkey, A.tallies);
+        wave_merge_add(dkey, A.tallies);
+    }
 }
 
 }  // namespace rpdla

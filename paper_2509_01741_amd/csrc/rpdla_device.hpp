@@ -91,8 +91,10 @@ __device__ inline double u01(uint64_t w) { return (double)((w >> 11) + 1ull) * 0
 // Variate j of atom `atom`: counter (atom, j/4, 0, 0), key (seed, cfg), word j%4.
 __device__ inline double uniform_j(uint64_t seed, uint32_t cfg, uint64_t atom, int j)
 {
-    U64x4 r = philox4x64(atom, (uint64_t)(j >> 2), 0, 0, seed, (uint64_t)cfg);
-    return u01(r.v[j & 3]);
+    const U64x4 r = philox4x64(atom, (uint64_t)(j >> 2), 0, 0, seed, (uint64_t)cfg);
+    const int w = j & 3;  // word select without a dynamically indexed array
+    const uint64_t v = (w == 0) ? r.v[0] : (w == 1) ? r.v[1] : (w == 2) ? r.v[2] : r.v[3];
+    return u01(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,12 +267,30 @@ __device__ inline double bound2_f64(const CFG& c, double X, double Y, double Z)
 // model without printing a formula): l = m = 0, l* = n* - 1, in log space,
 // per unit normalized time.  w = 0 when |a| = 0 or ln w < lnw_zero.
 // ---------------------------------------------------------------------------
+// Rate constants of one charge state, picked out of the configuration record
+// with static indices (no dynamic indexing into the record).
+struct AdkState {
+    double c0, c1h, c2, a2thr, lnw_zero;
+};
+
 template <class CFG>
-__device__ inline double adk_rate_n(const CFG& c, int s, double a2)
+__device__ inline AdkState adk_state(const CFG& c, int s)
+{
+    AdkState a{c.adk_c0[0], c.adk_c1h[0], c.adk_c2[0], c.adk_a2thr[0], c.lnw_zero};
+#pragma unroll
+    for (int i = 1; i < kMaxStates; ++i) {
+        if (s == i) {
+            a.c0 = c.adk_c0[i]; a.c1h = c.adk_c1h[i]; a.c2 = c.adk_c2[i]; a.a2thr = c.adk_a2thr[i];
+        }
+    }
+    return a;
+}
+
+__device__ inline double adk_rate_n(const AdkState& st, double a2)
 {
     if (!(a2 > 0.0)) return 0.0;
-    const double l = c.adk_c0[s] - c.adk_c1h[s] * log(a2) - c.adk_c2[s] * rsqrt(a2);
-    if (l < c.lnw_zero) return 0.0;
+    const double l = st.c0 - st.c1h * log(a2) - st.c2 * rsqrt(a2);
+    if (l < st.lnw_zero) return 0.0;
     return fm::exp_f64(l);
 }
 

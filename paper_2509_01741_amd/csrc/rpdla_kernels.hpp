@@ -47,36 +47,39 @@ __device__ inline double emag2_f64(const CFG& c, double X, double Y, double Z, d
 }
 
 template <int FIELD, class CFG>
-__device__ inline double rate_at(const CFG& c, int s, double X, double Y, double Z, double tau)
+__device__ inline double rate_at(const CFG& c, const AdkState& st, double X, double Y, double Z,
+                                 double tau)
 {
-    return adk_rate_n(c, s, emag2_f64<FIELD>(c, X, Y, Z, tau));
+    return adk_rate_n(st, emag2_f64<FIELD>(c, X, Y, Z, tau));
 }
 
+// GL-4 estimate of the integral of the rate over [a, b]; the nodes are
+// evaluated one after another (one field evaluation live at a time).
 template <int FIELD, class CFG>
-__device__ inline double gl4_integral(const CFG& c, int s, double X, double Y, double Z,
-                                      double a, double b)
+__device__ inline double gl4_integral(const CFG& c, const AdkState& st, double X, double Y,
+                                      double Z, double a, double b)
 {
     const double h = 0.5 * (b - a), m = 0.5 * (a + b);
     double acc = 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc += c.gl_w[i] * rate_at<FIELD>(c, s, X, Y, Z, m + h * c.gl_x[i]);
+#pragma unroll 1
+    for (int i = 0; i < 4; ++i) acc += c.gl_w[i] * rate_at<FIELD>(c, st, X, Y, Z, m + h * c.gl_x[i]);
     return h * acc;
 }
 
 template <int FIELD, class CFG>
-__device__ double solve_crossing(const CFG& c, int s, double X, double Y, double Z, double lo,
-                                 double hi, double target, double Ghi)
+__device__ double solve_crossing(const CFG& c, const AdkState& st, double X, double Y, double Z,
+                                 double lo, double hi, double target, double Ghi)
 {
     if (!(target > 0.0)) return lo;
     double tl = lo, th = hi;
     double t = lo + (hi - lo) * (target / Ghi);
     if (!(t > tl && t < th)) t = 0.5 * (tl + th);
     for (int it = 0; it < 100; ++it) {
-        const double gd = gl4_integral<FIELD>(c, s, X, Y, Z, lo, t) - target;
+        const double gd = gl4_integral<FIELD>(c, st, X, Y, Z, lo, t) - target;
         if (gd == 0.0) return t;
         if (gd > 0.0) th = t; else tl = t;
         const double tol = ldexp(fmax(fabs(t), kTwoPi), -40);
-        const double w = rate_at<FIELD>(c, s, X, Y, Z, t);
+        const double w = rate_at<FIELD>(c, st, X, Y, Z, t);
         double tn = __builtin_nan("");
         if (w > 0.0) {
             const double dlt = gd / w;
@@ -91,12 +94,12 @@ __device__ double solve_crossing(const CFG& c, int s, double X, double Y, double
     return t;
 }
 
-// Panel range [j_lo, j_hi] outside which state s has w = 0 at every node.
+// Panel range [j_lo, j_hi] outside which the state has w = 0 at every node.
 template <class CFG>
-__device__ inline bool state_window(const CFG& c, int s, double bound2, double Zc, double tau_s,
-                                    double h, int64_t M, int64_t& j_lo, int64_t& j_hi)
+__device__ inline bool state_window(const CFG& c, const AdkState& st, double bound2, double Zc,
+                                    double tau_s, double h, int64_t M, int64_t& j_lo, int64_t& j_hi)
 {
-    const double thr = c.adk_a2thr[s];
+    const double thr = st.a2thr;
     if (!(bound2 >= thr)) return false;            // never reaches a nonzero rate
     if (c.field == 11) { j_lo = 0; j_hi = M - 1; return true; }
     const double smax = sqrt(0.5 * log(bound2 / thr));
@@ -131,8 +134,9 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
         if (s < K) target = -log(uniform_j(seed, cfg, atom, k_first + s + 2));
     }
     if (s >= K) return;
+    AdkState st = adk_state(c, k_first - 1 + s);
     int64_t j_lo, j_hi;
-    if (!state_window(c, k_first - 1 + s, b2, Zc, tau_s, h, M, j_lo, j_hi)) return;
+    if (!state_window(c, st, b2, Zc, tau_s, h, M, j_lo, j_hi)) return;
     double I = 0.0;
     double tstart = tau_s;
     for (int64_t j = j_lo; j < M; ++j) {
@@ -141,19 +145,19 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
         const double b = (j == M - 1) ? tau_e : tau_s + (double)(j + 1) * h;
         bool done = false;
         while (true) {
-            const int ks = k_first - 1 + s;
             const double lo = (tstart > a) ? tstart : a;
-            const double seg = gl4_integral<FIELD>(c, ks, X, Y, Z, lo, b);
+            const double seg = gl4_integral<FIELD>(c, st, X, Y, Z, lo, b);
             if (I + seg < target) { I += seg; break; }
-            const double t = solve_crossing<FIELD>(c, ks, X, Y, Z, lo, b, target - I, seg);
+            const double t = solve_crossing<FIELD>(c, st, X, Y, Z, lo, b, target - I, seg);
             out[s] = t * c.inv_omega;
             ++s;
             if (s >= K) { done = true; break; }
             target = -log(uniform_j(seed, cfg, atom, k_first + s + 2));
             I = 0.0;
             tstart = t;
+            st = adk_state(c, k_first - 1 + s);
             int64_t nlo, nhi;
-            if (!state_window(c, k_first - 1 + s, b2, Zc, tau_s, h, M, nlo, nhi)) {
+            if (!state_window(c, st, b2, Zc, tau_s, h, M, nlo, nhi)) {
                 if (!(target > 0.0)) { j_hi = M - 1; continue; }
                 done = true;
                 break;
@@ -510,12 +514,13 @@ __device__ inline int64_t bin_key(const HistArgs& H, double tb, double ux, doubl
     return ((int64_t)dir * H.nE + (int64_t)fe) * H.nA + ia;
 }
 
-__device__ inline void wave_hist_commit(int64_t key, int tally, int dir,
-                                        unsigned long long* __restrict__ counts,
-                                        unsigned long long* __restrict__ tallies)
+// Add 1 at counter[key] for every lane with key >= 0, merging equal keys
+// across the wave first: the lowest pending lane's key is broadcast, the
+// lanes holding it are counted by ballot and one atomic adds the count.
+// Called by every lane of the wave.
+__device__ inline void wave_merge_add(int64_t key, unsigned long long* __restrict__ counter)
 {
     const int lane = __lane_id();
-    // aggregate equal keys
     bool pending = key >= 0;
     while (true) {
         const uint64_t act = __ballot(pending);
@@ -523,9 +528,17 @@ __device__ inline void wave_hist_commit(int64_t key, int tally, int dir,
         const int leader = __ffsll((unsigned long long)act) - 1;
         const int64_t lk = __shfl(key, leader);
         const uint64_t same = __ballot(pending && key == lk);
-        if (lane == leader) atomicAdd(&counts[lk], (unsigned long long)__popcll(same));
+        if (lane == leader) atomicAdd(&counter[lk], (unsigned long long)__popcll(same));
         if (pending && key == lk) pending = false;
     }
+}
+
+__device__ inline void wave_hist_commit(int64_t key, int tally, int dir,
+                                        unsigned long long* __restrict__ counts,
+                                        unsigned long long* __restrict__ tallies)
+{
+    const int lane = __lane_id();
+    wave_merge_add(key, counts);
     // tallies: 0 fwd, 1 bwd, 2 below, 3 above, 4 unborn, 5 NaN
     const uint64_t t0 = __ballot(dir == 0), t1 = __ballot(dir == 1);
     const uint64_t t2 = __ballot(tally == 2), t3 = __ballot(tally == 3);

@@ -71,7 +71,7 @@ class Ensemble:
 
 def run_sweep(wl: dict, precision: int, atoms_per_cfg: int | None = None,
               atoms_per_chunk: int | None = None, stream=None, workspace=None, counts=None,
-              tallies=None):
+              tallies=None, electron_steps=None):
     """Batched persistent sweep over every laser of a workload."""
     lasers = [laser_of(r, wl.get("field_order", 5)) for r in wl["lasers"]]
     n = int(atoms_per_cfg if atoms_per_cfg is not None else wl["atoms"])
@@ -79,4 +79,5 @@ def run_sweep(wl: dict, precision: int, atoms_per_cfg: int | None = None,
     apc = max(1, min(apc, n)) if n > 0 else 1
     return B.rpdla_run_batched(lasers, wl["seed"], wl["cfg_id"] * 1000, n, apc, wl["r_factor"],
                                wl["k_first"], wl["k_last"], precision, hist_spec(wl["hist"]),
-                               counts=counts, tallies=tallies, workspace=workspace, stream=stream)
+                               counts=counts, tallies=tallies, workspace=workspace, stream=stream,
+                               electron_steps=electron_steps)

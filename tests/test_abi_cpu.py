@@ -97,12 +97,12 @@ def test_validation_without_gpu():
     assert ws >= 64 * 65536 * (3 + 10) * 8
     arr = (B.rpdla_laser * 2)(L, L)
     sp = B.rpdla_hist_spec(4, 4, -3.0, 4.0, 0)
-    assert lib.rpdla_run_batched(arr, 65, 0, 0, 10, 10, 2.0, 1, 10, 0, C.byref(sp), p, p, p, 0,
-                                 p) == B.RPDLA_EUNSUPPORTED
+    assert lib.rpdla_run_batched(arr, 65, 0, 0, 10, 10, 2.0, 1, 10, 0, C.byref(sp), p, p, p, p,
+                                 0, p) == B.RPDLA_EUNSUPPORTED
     assert lib.rpdla_run_batched(arr, 2, 0, 0, 10, 10, 2.0, 1, 10, 0, C.byref(sp), C.c_void_p(256),
-                                 C.c_void_p(512), C.c_void_p(1024), 16, p) == B.RPDLA_ENOMEM
+                                 C.c_void_p(512), p, C.c_void_p(1024), 16, p) == B.RPDLA_ENOMEM
     arr[1].field = 1
-    assert lib.rpdla_run_batched(arr, 2, 0, 0, 10, 10, 2.0, 1, 10, 0, C.byref(sp), p, p, p, 0,
+    assert lib.rpdla_run_batched(arr, 2, 0, 0, 10, 10, 2.0, 1, 10, 0, C.byref(sp), p, p, p, p, 0,
                                  p) == B.RPDLA_EINVAL
     assert lib.rpdla_status_string(B.RPDLA_ENOMEM) == b"out of memory / workspace too small"
 
