@@ -178,6 +178,19 @@ rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots
                         double* uz, double* xf, double* yf, double* zf, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Per-electron outputs (text after Eq. (14); Sec. 2.2, Fig. 5): kinetic
+ * energy K = m c^2 u^2 / (gamma + 1) [MeV] (= (gamma - 1) m c^2 without
+ * cancellation), polar emission angle theta = atan2(|u_perp|, u_z), azimuth
+ * psi = atan2(u_y, u_x), forward flag 1 if u_z > 0 else 0 (-1 for NaN momenta,
+ * e.g. unborn slots, whose K, theta, psi are NaN).
+ * ux, uy, uz: device double[n] in; K_MeV, theta, psi: device double[n] out;
+ * fwd: device int32[n] out.  EINVAL: n < 0, null pointers with n > 0.
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_epilogue(int64_t n, const double* ux, const double* uy, const double* uz,
+                            double* K_MeV, double* theta, double* psi, int32_t* fwd,
+                            void* stream);
+
+/* ------------------------------------------------------------------------
  * Energy-angle histogram of n_slots electrons (see rpdla_hist_spec).
  * t_birth (to recognise unborn slots), ux, uy, uz: device double[n_slots].
  * counts: device uint64[2 * nE * nA] and tallies: device uint64[6], both
@@ -218,6 +231,32 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
                                int32_t precision, const rpdla_hist_spec* spec,
                                uint64_t* counts, uint64_t* tallies, uint64_t* electron_steps,
                                void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Launch-shape autotuning.  Kernel kinds: 0 push, 1 ionize, 2 batched push.
+ * A launch shape is the number of threads per block (64, 128, 192, 256) and,
+ * for the persistent push kernels, a factor on the resident-block count of
+ * the grid (1..8).  Shapes live in a process-wide table keyed by (kind,
+ * field model, precision; ionize ignores precision), default 256 x 1, and
+ * are read by every later launch.  Results never depend on the shape.
+ *
+ * rpdla_autotune samples a probe ensemble of n_atoms (64..2^24) for laser L
+ * and states k_first..k_last, times ionize for each block size and the push
+ * and the one-configuration batched push for each block size x grid factor
+ * 1, 2 (one untimed call before each timed one, HIP events on `stream`),
+ * stores the fastest shapes, and writes a JSON report of all timings to
+ * `report` (host buffer of report_len bytes, NUL-terminated, may be NULL).
+ * It allocates and frees its own probe buffers (hipMalloc) and synchronizes
+ * `stream` before returning.  rpdla_set_launch_shape / rpdla_get_launch_shape
+ * store / read one entry (for example to re-apply a saved report).
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_autotune(const rpdla_laser* L, int32_t precision, int64_t n_atoms,
+                            int32_t k_first, int32_t k_last, char* report, size_t report_len,
+                            void* stream);
+rpdla_status rpdla_set_launch_shape(int32_t kernel, int32_t field, int32_t precision,
+                                    int32_t block, int32_t grid_factor);
+rpdla_status rpdla_get_launch_shape(int32_t kernel, int32_t field, int32_t precision,
+                                    int32_t* block, int32_t* grid_factor);
 
 /* Status text and the calling thread's last error detail (never NULL). */
 const char* rpdla_status_string(rpdla_status s);

@@ -71,9 +71,13 @@ def _load():
         "rpdla_ionize": (i32, [LP, u64, u32, u64, i64, vp, vp, vp, i32, i32, vp, vp]),
         "rpdla_push": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
+        "rpdla_epilogue": (i32, [i64, vp, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_batched_workspace_bytes": (C.c_size_t, [i32, i64, i32, i32]),
         "rpdla_run_batched": (i32, [LP, i32, u64, u32, i64, i64, d, i32, i32, i32, HP, vp, vp,
                                     vp, vp, C.c_size_t, vp]),
+        "rpdla_autotune": (i32, [LP, i32, i64, i32, i32, C.c_char_p, C.c_size_t, vp]),
+        "rpdla_set_launch_shape": (i32, [i32, i32, i32, i32, i32]),
+        "rpdla_get_launch_shape": (i32, [i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "rpdla_status_string": (C.c_char_p, [i32]),
         "rpdla_last_error": (C.c_char_p, []),
         "rpdla_version": (C.c_char_p, []),
@@ -172,6 +176,19 @@ def rpdla_push(L, precision, t_birth, x0, y0, z0, slots_per_atom, out=None, stre
     return out
 
 
+def rpdla_epilogue(ux, uy, uz, out=None, stream=None):
+    """Returns (K_MeV, theta, psi, fwd) tensors for momenta ux, uy, uz."""
+    n = ux.numel()
+    if out is None:
+        out = (_empty(n, like=ux), _empty(n, like=ux), _empty(n, like=ux),
+               torch.empty(n, dtype=torch.int32, device=ux.device))
+    K, th, ps, fw = out
+    _check(lib.rpdla_epilogue(n, _dev(ux, "ux", n), _dev(uy, "uy", n), _dev(uz, "uz", n),
+                              _dev(K, "K", n), _dev(th, "theta", n), _dev(ps, "psi", n),
+                              _dev(fw, "fwd", n, torch.int32), _stream(stream)), "rpdla_epilogue")
+    return out
+
+
 def rpdla_histogram(t_birth, ux, uy, uz, spec: rpdla_hist_spec, counts=None, tallies=None,
                     stream=None):
     """counts: int64 tensor [2, nE, nA] and tallies: int64 tensor [6] (the
@@ -188,6 +205,30 @@ def rpdla_histogram(t_birth, ux, uy, uz, spec: rpdla_hist_spec, counts=None, tal
                                _dev(tallies, "tallies", RPDLA_NTALLY, torch.int64),
                                _stream(stream)), "rpdla_histogram")
     return counts, tallies
+
+
+RPDLA_KERNEL_PUSH, RPDLA_KERNEL_IONIZE, RPDLA_KERNEL_BATCHED_PUSH = 0, 1, 2
+
+
+def rpdla_autotune(L, precision, n_atoms=65536, k_first=1, k_last=10, stream=None) -> dict:
+    """Tune launch shapes for L's field model and `precision`; returns the report."""
+    import json
+    buf = C.create_string_buffer(8192)
+    _check(lib.rpdla_autotune(C.byref(L), precision, n_atoms, k_first, k_last, buf, len(buf),
+                              _stream(stream)), "rpdla_autotune")
+    return json.loads(buf.value.decode())
+
+
+def rpdla_set_launch_shape(kernel, field, precision, block, grid_factor=1):
+    _check(lib.rpdla_set_launch_shape(kernel, field, precision, block, grid_factor),
+           "rpdla_set_launch_shape")
+
+
+def rpdla_get_launch_shape(kernel, field, precision):
+    b, g = C.c_int32(), C.c_int32()
+    _check(lib.rpdla_get_launch_shape(kernel, field, precision, C.byref(b), C.byref(g)),
+           "rpdla_get_launch_shape")
+    return b.value, g.value
 
 
 def rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last) -> int:

@@ -8,9 +8,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <type_traits>
 
 #include "rpdla.h"
 #include "rpdla_kernels.hpp"
@@ -164,27 +167,44 @@ void laser_defaults(rpdla_laser* L, double lambda, double w0, double tau)
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Resident-wave count for a persistent launch of `kernel` with 256 lanes per block.
+// Launch shapes, per (kernel kind, field model, precision): threads per block
+// and, for persistent kernels, resident blocks per CU times grid_factor.
+// Filled by rpdla_autotune / rpdla_set_launch_shape; default 256 x 1.
+struct Shape { int block = 256; int grid_factor = 1; };
+std::mutex g_shape_mu;
+std::map<int, Shape> g_shapes;
+int shape_key(int kind, int field, int prec) { return (kind * 64 + field) * 4 + prec; }
+Shape get_shape(int kind, int field, int prec)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    auto it = g_shapes.find(shape_key(kind, field, prec));
+    return it == g_shapes.end() ? Shape() : it->second;
+}
+
+// Persistent grid: resident blocks (occupancy query) x grid_factor, capped by the work.
 template <typename K>
-int persistent_blocks(K kernel, int64_t work_items)
+int persistent_blocks(K kernel, int64_t work_items, int block, int grid_factor, size_t lds = 0)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    int64_t blocks = (int64_t)cus * per_cu;
-    const int64_t need = cdiv(work_items, 256);
+    int64_t blocks = (int64_t)cus * per_cu * grid_factor;
+    const int64_t need = cdiv(work_items, block);
     if (need < blocks) blocks = need;
     return (int)(blocks < 1 ? 1 : blocks);
 }
+
+constexpr int kKindPush = 0, kKindIonize = 1, kKindBatchPush = 2;
 
 template <int FIELD>
 rpdla_status launch_ionize(const DevCfg& c, uint64_t seed, uint32_t cfg, uint64_t first,
                            int64_t n, const double* x, const double* y, const double* z, int kf,
                            int kl, double* tb, hipStream_t st)
 {
-    hipLaunchKernelGGL(rpdla::ionize_kernel<FIELD>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st,
+    const int bs = get_shape(kKindIonize, FIELD, 0).block;
+    hipLaunchKernelGGL(rpdla::ionize_kernel<FIELD>, dim3((unsigned)cdiv(n, bs)), dim3(bs), 0, st,
                        c, seed, cfg, first, n, x, y, z, kf, kl, tb);
     RPDLA_HIP(hipGetLastError());
     return RPDLA_OK;
@@ -193,14 +213,15 @@ rpdla_status launch_ionize(const DevCfg& c, uint64_t seed, uint32_t cfg, uint64_
 template <int FIELD>
 rpdla_status launch_push(const DevCfg& c, int prec, const rpdla::PushIO& io, hipStream_t st)
 {
+    const Shape sh = get_shape(kKindPush, FIELD, prec);
     if (prec == RPDLA_FP64) {
         auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecF64>;
-        const int g = persistent_blocks(kern, io.n_slots);
-        hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, st, c, io);
+        const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
     } else {
         auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecMixed>;
-        const int g = persistent_blocks(kern, io.n_slots);
-        hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, st, c, io);
+        const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
     }
     RPDLA_HIP(hipGetLastError());
     return RPDLA_OK;
@@ -333,6 +354,18 @@ rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots
     return RPDLA_OK;
 }
 
+rpdla_status rpdla_epilogue(int64_t n, const double* ux, const double* uy, const double* uz,
+                            double* K_MeV, double* theta, double* psi, int32_t* fwd, void* stream)
+{
+    if (n < 0) return fail(RPDLA_EINVAL, "n < 0");
+    if (n == 0) return RPDLA_OK;
+    if (!ux || !uy || !uz || !K_MeV || !theta || !psi || !fwd) return fail(RPDLA_EINVAL, "null pointer");
+    hipLaunchKernelGGL(rpdla::epilogue_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0,
+                       (hipStream_t)stream, n, kMeC2MeV, ux, uy, uz, K_MeV, theta, psi, fwd);
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
 rpdla_status rpdla_histogram(int64_t n, const double* t_birth, const double* ux, const double* uy,
                              const double* uz, const rpdla_hist_spec* spec, uint64_t* counts,
                              uint64_t* tallies, void* stream)
@@ -405,14 +438,9 @@ rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipSt
     const size_t lds_p = (size_t)A.n_cfg * (sizeof(rpdla::PushCfg) + sizeof(unsigned long long));
     auto* kpush = rpdla::batch_push_kernel<FIELD, ELEC>;
     auto* kion = rpdla::batch_ionize_kernel<FIELD>;
-    int dev = 0, cus = 0, per_cu = 0;
-    RPDLA_HIP(hipGetDevice(&dev));
-    RPDLA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    RPDLA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kpush, 256, lds_p));
-    if (per_cu < 1) per_cu = 1;
+    const Shape sh = get_shape(kKindBatchPush, FIELD, std::is_same<ELEC, rpdla::ElecMixed>::value);
     const int64_t slots = (int64_t)A.n_cfg * A.apc * A.K;
-    int64_t grid_p = (int64_t)cus * per_cu;
-    if (cdiv(slots, 256) < grid_p) grid_p = cdiv(slots, 256);
+    const int64_t grid_p = persistent_blocks(kpush, slots, sh.block, sh.grid_factor, lds_p);
     const unsigned grid_a = (unsigned)cdiv((int64_t)A.n_cfg * A.apc, 256);
     int64_t grid_h = cdiv(slots, 256);
     if (grid_h > 8192) grid_h = 8192;
@@ -421,7 +449,7 @@ rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipSt
         hipLaunchKernelGGL(rpdla::batch_zero_queue_kernel, dim3(1), dim3(64), 0, st, A.ctl);
         hipLaunchKernelGGL(rpdla::batch_sample_kernel, dim3(grid_a), dim3(256), 0, st, A);
         hipLaunchKernelGGL(kion, dim3(grid_a), dim3(256), lds_i, st, A);
-        hipLaunchKernelGGL(kpush, dim3((unsigned)grid_p), dim3(256), lds_p, st, A);
+        hipLaunchKernelGGL(kpush, dim3((unsigned)grid_p), dim3(sh.block), lds_p, st, A);
         hipLaunchKernelGGL(rpdla::batch_hist_kernel, dim3((unsigned)grid_h), dim3(256), 0, st, A);
         hipLaunchKernelGGL(rpdla::batch_advance_kernel, dim3(1), dim3(64), 0, st, A.ctl);
         RPDLA_HIP(hipGetLastError());
@@ -444,6 +472,7 @@ rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipSt
     key.append(reinterpret_cast<const char*>(tag), sizeof tag);
     key.append(reinterpret_cast<const char*>(&s), sizeof s);
     key.append(reinterpret_cast<const char*>(&grid_p), sizeof grid_p);
+    key.append(reinterpret_cast<const char*>(&sh), sizeof sh);
     hipGraphExec_t exec = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -565,6 +594,176 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
     default: return mixed ? run_batched_impl<11, rpdla::ElecMixed>(A, n_chunks, s)
                           : run_batched_impl<11, rpdla::ElecF64>(A, n_chunks, s);
     }
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Launch-shape autotuning
+// ===========================================================================
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+// Time one enqueue of `fn` on stream s (after one untimed call), in ms.
+template <class F>
+rpdla_status time_ms(hipStream_t s, F fn, float* ms)
+{
+    rpdla_status st = fn();
+    if (st != RPDLA_OK) return st;
+    hipEvent_t a, b;
+    RPDLA_HIP(hipEventCreate(&a));
+    RPDLA_HIP(hipEventCreate(&b));
+    RPDLA_HIP(hipEventRecord(a, s));
+    st = fn();
+    RPDLA_HIP(hipEventRecord(b, s));
+    RPDLA_HIP(hipEventSynchronize(b));
+    RPDLA_HIP(hipEventElapsedTime(ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
+}
+
+void set_shape(int kind, int field, int prec, Shape sh)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shapes[shape_key(kind, field, prec)] = sh;
+}
+
+}  // namespace
+
+extern "C" {
+
+rpdla_status rpdla_set_launch_shape(int32_t kernel, int32_t field, int32_t precision, int32_t block,
+                                    int32_t grid_factor)
+{
+    if (kernel < 0 || kernel > 2) return fail(RPDLA_EINVAL, "kernel must be 0 (push), 1 (ionize) or 2 (batched push)");
+    if (!(field == 1 || field == 3 || field == 5 || field == 10 || field == 11))
+        return fail(RPDLA_EINVAL, "unknown field model %d", field);
+    if (!(precision == RPDLA_FP64 || precision == RPDLA_MIXED)) return fail(RPDLA_EINVAL, "unknown precision");
+    if (!(block == 64 || block == 128 || block == 192 || block == 256))
+        return fail(RPDLA_EINVAL, "block must be 64, 128, 192 or 256");
+    if (grid_factor < 1 || grid_factor > 8) return fail(RPDLA_EINVAL, "grid_factor must be 1..8");
+    set_shape(kernel, field, kernel == kKindIonize ? 0 : precision, Shape{block, grid_factor});
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_get_launch_shape(int32_t kernel, int32_t field, int32_t precision, int32_t* block,
+                                    int32_t* grid_factor)
+{
+    if (!block || !grid_factor) return fail(RPDLA_EINVAL, "null pointer");
+    if (kernel < 0 || kernel > 2) return fail(RPDLA_EINVAL, "unknown kernel");
+    const Shape sh = get_shape(kernel, field, kernel == kKindIonize ? 0 : precision);
+    *block = sh.block;
+    *grid_factor = sh.grid_factor;
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_autotune(const rpdla_laser* L, int32_t precision, int64_t n_atoms, int32_t k_first,
+                            int32_t k_last, char* report, size_t report_len, void* stream)
+{
+    rpdla_status st = check_laser(L);
+    if (st != RPDLA_OK) return st;
+    if (!(precision == RPDLA_FP64 || precision == RPDLA_MIXED)) return fail(RPDLA_EINVAL, "unknown precision");
+    if (!(1 <= k_first && k_first <= k_last && k_last <= 10)) return fail(RPDLA_EINVAL, "bad charge-state range");
+    if (n_atoms < 64 || n_atoms > (1 << 24)) return fail(RPDLA_ERANGE, "probe size must be 64..2^24 atoms");
+    hipStream_t s = (hipStream_t)stream;
+    const int K = k_last - k_first + 1;
+    const int64_t ns = n_atoms * K;
+    DevBuf bx, by, bz, btb, bo[6], bcnt, btal, bws;
+    RPDLA_HIP(hipMalloc(&bx.p, n_atoms * 8)); RPDLA_HIP(hipMalloc(&by.p, n_atoms * 8));
+    RPDLA_HIP(hipMalloc(&bz.p, n_atoms * 8)); RPDLA_HIP(hipMalloc(&btb.p, ns * 8));
+    for (auto& b : bo) RPDLA_HIP(hipMalloc(&b.p, ns * 8));
+    double* x = (double*)bx.p; double* y = (double*)by.p; double* z = (double*)bz.p;
+    double* tb = (double*)btb.p;
+    double* o[6];
+    for (int i = 0; i < 6; ++i) o[i] = (double*)bo[i].p;
+    st = rpdla_sample_atoms(0x5eedull, 0xA070u, 0, n_atoms, 2.0 * L->w0, rpdla_rayleigh(L), x, y, z, stream);
+    if (st != RPDLA_OK) return st;
+    const int field = L->field;
+    const int blocks[3] = {64, 128, 256};
+    std::string js = "{\"field\": " + std::to_string(field) + ", \"precision\": " + std::to_string(precision) +
+                     ", \"atoms\": " + std::to_string(n_atoms);
+    // ionize: threads per block
+    {
+        const Shape keep = get_shape(kKindIonize, field, 0);
+        float best = 1e30f; Shape bsh = keep;
+        js += ", \"ionize_ms\": {";
+        for (int bi = 0; bi < 3; ++bi) {
+            set_shape(kKindIonize, field, 0, Shape{blocks[bi], 1});
+            float ms = 0;
+            st = time_ms(s, [&] { return rpdla_ionize(L, 0x5eedull, 0xA070u, 0, n_atoms, x, y, z,
+                                                      k_first, k_last, tb, stream); }, &ms);
+            if (st != RPDLA_OK) { set_shape(kKindIonize, field, 0, keep); return st; }
+            js += (bi ? ", \"" : "\"") + std::to_string(blocks[bi]) + "x1\": " + std::to_string(ms);
+            if (ms < best) { best = ms; bsh = Shape{blocks[bi], 1}; }
+        }
+        set_shape(kKindIonize, field, 0, bsh);
+        js += "}, \"ionize_best\": \"" + std::to_string(bsh.block) + "x1\"";
+    }
+    // push: threads per block x persistent grid factor
+    {
+        const Shape keep = get_shape(kKindPush, field, precision);
+        float best = 1e30f; Shape bsh = keep;
+        js += ", \"push_ms\": {";
+        bool firstc = true;
+        for (int bi = 0; bi < 3; ++bi) {
+            for (int gf = 1; gf <= 2; ++gf) {
+                set_shape(kKindPush, field, precision, Shape{blocks[bi], gf});
+                float ms = 0;
+                st = time_ms(s, [&] { return rpdla_push(L, precision, ns, tb, x, y, z, K, o[0], o[1], o[2],
+                                                        o[3], o[4], o[5], stream); }, &ms);
+                if (st != RPDLA_OK) { set_shape(kKindPush, field, precision, keep); return st; }
+                js += (firstc ? "\"" : ", \"") + std::to_string(blocks[bi]) + "x" + std::to_string(gf) +
+                      "\": " + std::to_string(ms);
+                firstc = false;
+                if (ms < best) { best = ms; bsh = Shape{blocks[bi], gf}; }
+            }
+        }
+        set_shape(kKindPush, field, precision, bsh);
+        js += "}, \"push_best\": \"" + std::to_string(bsh.block) + "x" + std::to_string(bsh.grid_factor) + "\"";
+    }
+    // batched push (one configuration through the batched path)
+    {
+        rpdla_hist_spec sp{64, 36, -3.0, 4.0, RPDLA_ANG_POLAR};
+        const size_t wsb = rpdla_batched_workspace_bytes(1, n_atoms, k_first, k_last);
+        RPDLA_HIP(hipMalloc(&bws.p, wsb));
+        RPDLA_HIP(hipMalloc(&bcnt.p, 2 * 64 * 36 * 8));
+        RPDLA_HIP(hipMalloc(&btal.p, 6 * 8));
+        const Shape keep = get_shape(kKindBatchPush, field, precision);
+        float best = 1e30f; Shape bsh = keep;
+        js += ", \"batched_push_ms\": {";
+        bool firstc = true;
+        for (int bi = 0; bi < 3; ++bi) {
+            for (int gf = 1; gf <= 2; ++gf) {
+                set_shape(kKindBatchPush, field, precision, Shape{blocks[bi], gf});
+                float ms = 0;
+                st = time_ms(s, [&] {
+                    return rpdla_run_batched(L, 1, 0x5eedull, 0xA070u, n_atoms, n_atoms, 2.0, k_first, k_last,
+                                             precision, &sp, (uint64_t*)bcnt.p, (uint64_t*)btal.p, nullptr,
+                                             bws.p, wsb, stream);
+                }, &ms);
+                if (st != RPDLA_OK) { set_shape(kKindBatchPush, field, precision, keep); return st; }
+                js += (firstc ? "\"" : ", \"") + std::to_string(blocks[bi]) + "x" + std::to_string(gf) +
+                      "\": " + std::to_string(ms);
+                firstc = false;
+                if (ms < best) { best = ms; bsh = Shape{blocks[bi], gf}; }
+            }
+        }
+        set_shape(kKindBatchPush, field, precision, bsh);
+        js += "}, \"batched_push_best\": \"" + std::to_string(bsh.block) + "x" + std::to_string(bsh.grid_factor) + "\"";
+    }
+    RPDLA_HIP(hipStreamSynchronize(s));
+    js += "}";
+    if (report && report_len > 0) {
+        const size_t m = js.size() < report_len - 1 ? js.size() : report_len - 1;
+        memcpy(report, js.data(), m);
+        report[m] = 0;
+    }
+    return RPDLA_OK;
 }
 
 }  // extern "C"

@@ -570,6 +570,25 @@ __global__ void __launch_bounds__(256) histogram_kernel(
     }
 }
 
+// Per-electron outputs: kinetic energy m c^2 u^2/(gamma + 1) [MeV], polar
+// angle atan2(|u_perp|, u_z), azimuth atan2(u_y, u_x), forward flag u_z > 0.
+// NaN momenta give NaN energy and angles and flag -1.
+__global__ void __launch_bounds__(256) epilogue_kernel(
+    int64_t n, double mec2, const double* __restrict__ ux, const double* __restrict__ uy,
+    const double* __restrict__ uz, double* __restrict__ K, double* __restrict__ theta,
+    double* __restrict__ psi, int32_t* __restrict__ fwd)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = ux[i], y = uy[i], z = uz[i];
+    const double up2 = x * x + y * y;
+    const double u2 = up2 + z * z;
+    K[i] = mec2 * u2 / (sqrt(1.0 + u2) + 1.0);
+    theta[i] = atan2(sqrt(up2), z);
+    psi[i] = atan2(y, x);
+    fwd[i] = (isnan(x) || isnan(y) || isnan(z)) ? -1 : (z > 0.0 ? 1 : 0);
+}
+
 __global__ void zero_u64_kernel(unsigned long long* p, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -85,6 +85,10 @@ def test_validation_without_gpu():
     assert lib.rpdla_histogram(4, p, p, p, p, C.byref(sp), p, p, p) == B.RPDLA_EINVAL
     sp = B.rpdla_hist_spec(4, 4, 4.0, -3.0, 0)
     assert lib.rpdla_histogram(4, p, p, p, p, C.byref(sp), p, p, p) == B.RPDLA_EINVAL
+    # epilogue
+    assert lib.rpdla_epilogue(-1, p, p, p, p, p, p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_epilogue(3, p, p, p, p, p, p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_epilogue(0, p, p, p, p, p, p, p, p) == B.RPDLA_OK
     # sampling
     assert lib.rpdla_sample_atoms(0, 0, 0, -1, 1.0, 1.0, p, p, p, p) == B.RPDLA_EINVAL
     assert lib.rpdla_sample_atoms(0, 0, 0, 5, -1.0, 1.0, p, p, p, p) == B.RPDLA_EINVAL
@@ -105,6 +109,15 @@ def test_validation_without_gpu():
     assert lib.rpdla_run_batched(arr, 2, 0, 0, 10, 10, 2.0, 1, 10, 0, C.byref(sp), p, p, p, p, 0,
                                  p) == B.RPDLA_EINVAL
     assert lib.rpdla_status_string(B.RPDLA_ENOMEM) == b"out of memory / workspace too small"
+    # launch-shape table (host only)
+    assert lib.rpdla_set_launch_shape(0, 5, 0, 100, 1) == B.RPDLA_EINVAL
+    assert lib.rpdla_set_launch_shape(3, 5, 0, 128, 1) == B.RPDLA_EINVAL
+    assert lib.rpdla_set_launch_shape(0, 5, 0, 128, 9) == B.RPDLA_EINVAL
+    assert B.rpdla_get_launch_shape(0, 3, 1) == (256, 1)
+    B.rpdla_set_launch_shape(0, 3, 1, 128, 2)
+    assert B.rpdla_get_launch_shape(0, 3, 1) == (128, 2)
+    B.rpdla_set_launch_shape(0, 3, 1, 256, 1)
+    assert lib.rpdla_autotune(C.byref(L), 0, 10, 1, 10, None, 0, p) == B.RPDLA_ERANGE
 
 
 def test_ne_table_matches_oracle(orc):

@@ -210,6 +210,43 @@ def test_mixed_vs_fp64(env):
     assert np.mean(fa == fb) >= 0.99
 
 
+def test_autotune_and_shape_independence(env):
+    """The autotuner reports timings and stores a shape; results do not
+    depend on the launch shape (bitwise)."""
+    torch, B, O = env
+    L, _ = _lasers(B, O, 5)
+    rep = B.rpdla_autotune(L, 0, 4096, 1, 10)
+    assert rep["field"] == 5 and len(rep["push_ms"]) == 6 and len(rep["ionize_ms"]) == 3
+    n, K = 300, 10
+    x, y, z = B.rpdla_sample_atoms(0, 4, 0, n, 2 * L.w0, B.rpdla_rayleigh(L))
+    outs = []
+    for blk, gf in ((64, 1), (256, 2), (128, 1)):
+        B.rpdla_set_launch_shape(B.RPDLA_KERNEL_IONIZE, 5, 0, blk, 1)
+        B.rpdla_set_launch_shape(B.RPDLA_KERNEL_PUSH, 5, 0, blk, gf)
+        tb = B.rpdla_ionize(L, 0, 4, 0, x, y, z, 1, K)
+        o = B.rpdla_push(L, 0, tb, x, y, z, K)
+        outs.append([tb.cpu().numpy()] + [a.cpu().numpy() for a in o])
+    B.rpdla_set_launch_shape(B.RPDLA_KERNEL_IONIZE, 5, 0, 256, 1)
+    B.rpdla_set_launch_shape(B.RPDLA_KERNEL_PUSH, 5, 0, 256, 1)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b, equal_nan=True)
+
+
+def test_epilogue_parity(env):
+    torch, B, O = env
+    rng = np.random.default_rng(12)
+    n = 5000
+    u = rng.normal(size=(n, 3)) * np.exp(rng.uniform(-8, 8, size=(n, 1)))
+    u[:3] = [[0, 0, 0], [0, 0, -2.0], [1e-9, 0, 0]]
+    u[3] = np.nan
+    K, th, ps, fw = (o.cpu().numpy() for o in B.rpdla_epilogue(*(_t(torch, u[:, i]) for i in range(3))))
+    oK, oth, ops, ofw = O.epilogue(u[4:, 0], u[4:, 1], u[4:, 2])
+    assert np.all(np.abs(K[4:] - oK) <= 1e-15 * oK + 1e-300)
+    assert np.all(np.abs(th[4:] - oth) <= 1e-15) and np.all(np.abs(ps[4:] - ops) <= 1e-15)
+    assert np.array_equal(fw[4:], ofw) and fw[3] == -1 and np.isnan(K[3])
+
+
 def test_histogram_exact(env):
     torch, B, O = env
     rng = np.random.default_rng(11)
