@@ -193,7 +193,7 @@ __device__ inline void rhs_f64(const CFG& c, double tau, double X, double Y, dou
 {
     double ax, ay, az, bx, by, bz;
     field_f64<FIELD, true, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
-    const double ig = rsqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    const double ig = fm::rsqrt_ge1_f64(1.0 + ux * ux + uy * uy + uz * uz);
     dX = ux * ig; dY = uy * ig; dZ = uz * ig;
     dux = -(ax + dY * bz - dZ * by);
     duy = -(ay + dZ * bx - dX * bz);

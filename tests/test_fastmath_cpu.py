@@ -24,6 +24,9 @@ extern "C" void fm_exp(long n, const double* x, double* y) {
 extern "C" void fm_rcp(long n, const double* x, double* y) {
     for (long i = 0; i < n; ++i) y[i] = rpdla::fm::rcp_f64(x[i]);
 }
+extern "C" void fm_rsqrt(long n, const double* x, double* y) {
+    for (long i = 0; i < n; ++i) y[i] = rpdla::fm::rsqrt_ge1_f64(x[i]);
+}
 '''
 
 
@@ -40,6 +43,7 @@ def fm(tmp_path_factory):
     lib.fm_sincos.argtypes = [C.c_long, P, P, P]
     lib.fm_exp.argtypes = [C.c_long, P, P]
     lib.fm_rcp.argtypes = [C.c_long, P, P]
+    lib.fm_rsqrt.argtypes = [C.c_long, P, P]
     return lib
 
 
@@ -90,6 +94,16 @@ def test_rcp(fm):
     fm.fm_rcp(x.size, x, y)
     rel = np.abs(y - 1.0 / x) * x
     assert rel.max() <= 2 * 2.0**-53
+
+
+def test_rsqrt(fm):
+    rng = np.random.default_rng(5)
+    x = np.concatenate([1.0 + rng.uniform(0, 10, 100000) ** 2, np.exp(rng.uniform(0, 40, 100000)),
+                        [1.0, 2.0, 4.0, 1e30]])
+    y = np.zeros_like(x)
+    fm.fm_rsqrt(x.size, x, y)
+    rel = np.abs(y - 1.0 / np.sqrt(x)) * np.sqrt(x)
+    assert rel.max() <= 3 * 2.0**-53, rel.max()  # reference 1/sqrt rounds twice
 
 
 def test_coefficients_are_the_generator_output():
