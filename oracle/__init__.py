@@ -93,6 +93,9 @@ def lib():
         "orc_epilogue": (None, [C.c_int64, _D, _D, _D, _D, _D, _D, _I32]),
         "orc_histogram": (None, [C.c_int64, _D, _D, _D, _D, C.POINTER(HistSpec), _U64, _U64]),
         "orc_num_threads": (C.c_int, []),
+        "orc_birth_phase": (None, [LP, C.c_int64, _D, _D, _D, _D, C.c_int, _D]),
+        "orc_sample_atoms_annulus": (None, [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64,
+                                            C.c_double, C.c_double, C.c_double, _D, _D, _D]),
         "orc_ne_ip_table": (C.POINTER(C.c_double), []),
     }
     for name, (res, args) in sig.items():
@@ -242,6 +245,19 @@ def histogram(t_birth, ux, uy, uz, nE, nA, logE_min, logE_max, angle=ANG_POLAR):
     lib().orc_histogram(t_birth.size, t_birth, _d(ux), _d(uy), _d(uz), C.byref(sp),
                         counts, tallies)
     return counts.reshape(2, nE, nA), tallies
+
+
+def birth_phase(L: Laser, t_birth, x, y, z, slots_per_atom):
+    t_birth = _d(t_birth)
+    ph = np.zeros(t_birth.size)
+    lib().orc_birth_phase(C.byref(L), t_birth.size, t_birth, _d(x), _d(y), _d(z), slots_per_atom, ph)
+    return ph
+
+
+def sample_atoms_annulus(seed, cfg, first_atom, n, r_in, r_out, z_half):
+    x, y, z = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_sample_atoms_annulus(seed, cfg, first_atom, n, r_in, r_out, z_half, x, y, z)
+    return x, y, z
 
 
 def num_threads() -> int:

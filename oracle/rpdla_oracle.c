@@ -607,3 +607,54 @@ void orc_adk_rate_batch(int k, int64_t n, const double* Emag, double* w)
 {
     for (int64_t i = 0; i < n; ++i) w[i] = orc_adk_rate(k, Emag[i]);
 }
+
+/* ---------------------------------------------------------------------------
+ * Laser phase at a birth event (Sec. 2.2, Figs. 6, 13, 14: "initial phase of
+ * the laser coincident with the birth"): the phase defined under Eq. (2),
+ *   phi = k z - omega t - 2 atan(z/z_r) + z r^2 / (z_r r0^2 f^2) + phi0,
+ * f^2 = 1 + (z/z_r)^2, with the paper's phi0 = -(this library's phi0)
+ * (reading of the carrier-phase sign), reduced to [0, 2 pi).  NaN for
+ * unborn slots.  Slot s belongs to atom s / slots_per_atom.
+ * ------------------------------------------------------------------------- */
+double orc_birth_phase_one(const orc_laser* L, double x, double y, double z, double t)
+{
+    const double k = 2.0 * ORC_PI / L->lambda;
+    const double om = ORC_C * k;
+    const double zr = 0.5 * k * L->w0 * L->w0;
+    const double r2 = x * x + y * y;
+    const double f2 = 1.0 + (z / zr) * (z / zr);
+    double phi = k * z - om * t - 2.0 * atan(z / zr) + z * r2 / (zr * L->w0 * L->w0 * f2) - L->phi0;
+    phi = fmod(phi, 2.0 * ORC_PI);
+    if (phi < 0.0) phi += 2.0 * ORC_PI;
+    if (phi >= 2.0 * ORC_PI) phi -= 2.0 * ORC_PI;
+    return phi;
+}
+
+void orc_birth_phase(const orc_laser* L, int64_t n_slots, const double* t_birth, const double* x,
+                     const double* y, const double* z, int slots_per_atom, double* phase)
+{
+    for (int64_t s = 0; s < n_slots; ++s) {
+        int64_t a = s / slots_per_atom;
+        phase[s] = (t_birth[s] < INFINITY) ? orc_birth_phase_one(L, x[a], y[a], z[a], t_birth[s]) : NAN;
+    }
+}
+
+/* Annular sampling (Sec. 2.2, Fig. 8: ions uniform on the surface of a hollow
+ * cylinder): r uniform in area between r_in and r_out, r = r_out exactly when
+ * r_in == r_out (a surface); azimuth and z as in orc_sample_atoms. */
+void orc_sample_atoms_annulus(uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n,
+                              double r_in, double r_out, double z_half, double* x, double* y,
+                              double* z)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t a = first_atom + (uint64_t)i;
+        double u0 = orc_uniform(seed, cfg, a, 0);
+        double u1 = orc_uniform(seed, cfg, a, 1);
+        double u2 = orc_uniform(seed, cfg, a, 2);
+        double r = (r_in == r_out) ? r_out : sqrt(r_in * r_in + u0 * (r_out * r_out - r_in * r_in));
+        double th = 2.0 * ORC_PI * u1;
+        x[i] = r * cos(th);
+        y[i] = r * sin(th);
+        z[i] = z_half * (2.0 * u2 - 1.0);
+    }
+}
