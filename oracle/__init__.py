@@ -96,6 +96,8 @@ def lib():
         "orc_birth_phase": (None, [LP, C.c_int64, _D, _D, _D, _D, C.c_int, _D]),
         "orc_sample_atoms_annulus": (None, [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64,
                                             C.c_double, C.c_double, C.c_double, _D, _D, _D]),
+        "orc_histogram2d": (None, [C.c_int64, _D, _D, _D, C.c_int32, C.c_double, C.c_double,
+                                   C.c_int32, C.c_double, C.c_double, _U64, _U64]),
         "orc_ne_ip_table": (C.POINTER(C.c_double), []),
     }
     for name, (res, args) in sig.items():
@@ -258,6 +260,16 @@ def sample_atoms_annulus(seed, cfg, first_atom, n, r_in, r_out, z_half):
     x, y, z = np.zeros(n), np.zeros(n), np.zeros(n)
     lib().orc_sample_atoms_annulus(seed, cfg, first_atom, n, r_in, r_out, z_half, x, y, z)
     return x, y, z
+
+
+def histogram2d(a, b, uz, na, a_lo, a_hi, nb, b_lo, b_hi):
+    """counts uint64 [2, na, nb] (0 forward: uz > 0) and tallies [2]
+    (0 outside the ranges, 1 NaN)."""
+    a, b, uz = _d(a), _d(b), _d(uz)
+    counts = np.zeros((2, na, nb), dtype=np.uint64)
+    tallies = np.zeros(2, dtype=np.uint64)
+    lib().orc_histogram2d(a.size, a, b, uz, na, a_lo, a_hi, nb, b_lo, b_hi, counts, tallies)
+    return counts, tallies
 
 
 def num_threads() -> int:

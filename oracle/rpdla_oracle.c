@@ -658,3 +658,31 @@ void orc_sample_atoms_annulus(uint64_t seed, uint32_t cfg, uint64_t first_atom, 
         z[i] = z_half * (2.0 * u2 - 1.0);
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Two-dimensional histogram split by the direction of final motion, for the
+ * birth-phase x birth-radius maps of forward and backward electrons (Sec. 2.2,
+ * Figs. 13, 14) and the birth-variable x energy maps of Fig. 6.  Pair i goes
+ * to counts[dir][ia][ib] with dir 0 if uz[i] > 0 else 1,
+ * ia = floor((a[i] - a_lo) / ((a_hi - a_lo) / na)), ib likewise; pairs with a
+ * NaN in a, b or uz are tallied in tallies[1], pairs outside the ranges in
+ * tallies[0].  Counts and tallies accumulate.
+ * ------------------------------------------------------------------------- */
+void orc_histogram2d(int64_t n, const double* a, const double* b, const double* uz,
+                     int32_t na, double a_lo, double a_hi, int32_t nb, double b_lo,
+                     double b_hi, uint64_t* counts, uint64_t* tallies)
+{
+    const double wa = (a_hi - a_lo) / (double)na;
+    const double wb = (b_hi - b_lo) / (double)nb;
+    for (int64_t i = 0; i < n; ++i) {
+        if (isnan(a[i]) || isnan(b[i]) || isnan(uz[i])) { tallies[1] += 1; continue; }
+        const double fa = floor((a[i] - a_lo) / wa);
+        const double fb = floor((b[i] - b_lo) / wb);
+        if (!(fa >= 0.0 && fa < (double)na && fb >= 0.0 && fb < (double)nb)) {
+            tallies[0] += 1;
+            continue;
+        }
+        const int dir = (uz[i] > 0.0) ? 0 : 1;
+        counts[((int64_t)dir * na + (int64_t)fa) * nb + (int64_t)fb] += 1;
+    }
+}

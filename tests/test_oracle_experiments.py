@@ -93,3 +93,57 @@ def test_annulus_reduces_to_filled_cylinder(orc):
     b = orc.sample_atoms_annulus(3, 1, 100, 5000, 0.0, 3e-6, 7e-6)
     for u, v in zip(a, b):   # r_max sqrt(u) vs sqrt(u r_max^2): a rounding apart
         assert np.max(np.abs(u - v)) <= 4 * np.finfo(float).eps * 3e-6
+
+
+def _brute_hist2d(a, b, uz, na, alo, ahi, nb, blo, bhi):
+    """Pure-Python loop over explicit bin edges (small inputs only)."""
+    ea = [alo + (ahi - alo) * i / na for i in range(na + 1)]
+    eb = [blo + (bhi - blo) * i / nb for i in range(nb + 1)]
+    counts = np.zeros((2, na, nb), dtype=np.uint64)
+    out = nan = 0
+    for ai, bi, ui in zip(a, b, uz):
+        if np.isnan(ai) or np.isnan(bi) or np.isnan(ui):
+            nan += 1
+            continue
+        ia = next((i for i in range(na) if ea[i] <= ai < ea[i + 1]), None)
+        ib = next((i for i in range(nb) if eb[i] <= bi < eb[i + 1]), None)
+        if ia is None or ib is None:
+            out += 1
+            continue
+        counts[0 if ui > 0 else 1, ia, ib] += 1
+    return counts, out, nan
+
+
+def test_histogram2d_brute_force(orc):
+    rng = np.random.default_rng(11)
+    n = 3000
+    a = rng.uniform(-0.5, 2 * np.pi + 0.5, n)
+    b = rng.uniform(-1e-7, 4.2e-6, n)
+    uz = rng.normal(size=n)
+    uz[::97] = 0.0          # exactly zero counts as backward
+    a[5::131] = np.nan
+    uz[7::173] = np.nan
+    # keep values away from bin edges, where the two bin rules may round apart
+    wa, wb = 2 * np.pi / 24, 4e-6 / 16
+    for v, lo, w in ((a, 0.0, wa), (b, 0.0, wb)):
+        f = (v - lo) / w
+        near = np.abs(f - np.round(f)) < 1e-9
+        v[near] += 0.25 * w
+    counts, tallies = orc.histogram2d(a, b, uz, 24, 0.0, 2 * np.pi, 16, 0.0, 4e-6)
+    bc, out, nan = _brute_hist2d(a, b, uz, 24, 0.0, 2 * np.pi, 16, 0.0, 4e-6)
+    assert np.array_equal(counts, bc)
+    assert tallies[0] == out and tallies[1] == nan
+    assert counts.sum() + out + nan == n
+    assert counts[1].sum() >= np.count_nonzero(uz == 0.0)
+
+
+def test_histogram2d_matches_numpy(orc):
+    rng = np.random.default_rng(12)
+    a = rng.uniform(0, 1, 5000)
+    b = rng.uniform(0, 1, 5000)
+    uz = np.ones(5000)
+    c1, t1 = orc.histogram2d(a, b, uz, 8, 0.0, 1.0, 5, 0.0, 1.0)
+    ref, _, _ = np.histogram2d(a, b, bins=(8, 5), range=((0, 1), (0, 1)))
+    assert np.array_equal(c1[0], ref.astype(np.uint64)) and c1[1].sum() == 0
+    c2, t2 = orc.histogram2d(-uz, b, -uz, 1, -2.0, 0.0, 1, 0.0, 1.0)
+    assert c2[1, 0, 0] == 5000 and t2.sum() == 0
