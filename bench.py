@@ -64,31 +64,35 @@ def electron_steps(tb, z, K, L):
 
 
 def cpu_baseline(ens, budget_s=15.0):
-    """Oracle push rate on a bounded sample of the same ensemble (the slots of
-    the first atoms, with the GPU's birth times), scaled to ~budget_s."""
+    """Oracle push rate on a bounded sample of the same workload: the oracle
+    samples the first atoms and ionizes them itself (same seed and laser), and
+    its push over their slots is timed, scaled to ~budget_s."""
     import numpy as np
     import oracle as O
-    rec = ens.wl["lasers"][0]
+    wl = ens.wl
+    rec = wl["lasers"][0]
     OL = O.laser_intensity(rec["lam"], rec["w0"], rec["tau"], rec["I"])
     OL.field = ens.L.field
-    K = ens.K
-    tb = ens.tb.cpu().numpy()
-    x, y, z = (a.cpu().numpy() for a in (ens.x, ens.y, ens.z))
+    kf, kl = wl["k_first"], wl["k_last"]
+    K = kl - kf + 1
 
     def run(na):
-        t = tb[: na * K]
+        x, y, z = O.sample_atoms(wl["seed"], wl["cfg_id"], 0, na, wl["r_factor"] * OL.w0,
+                                 O.rayleigh(OL))
+        t = O.ionize(OL, wl["seed"], wl["cfg_id"], 0, x, y, z, kf, kl)
         fin = np.isfinite(t)
-        steps = np.ceil((np.repeat(z[:na], K)[fin] / C_LIGHT + OL.t_after - t[fin]) / OL.dt).sum()
+        steps = np.ceil((np.repeat(z, K)[fin] / C_LIGHT + OL.t_after - t[fin]) / OL.dt).sum()
         t0 = time.perf_counter()
-        O.push(OL, t, x[:na], y[:na], z[:na], K)
+        O.push(OL, t, x, y, z, K)
         return float(steps), time.perf_counter() - t0
 
     s1, t1 = run(4)
-    na = int(max(4, min(len(x), 4 * budget_s / max(t1, 1e-3))))
+    na = int(max(4, min(ens.n, 4 * budget_s / max(t1, 1e-3))))
     s2, t2 = run(na)
     return dict(value=s2 / t2, unit="electron-steps/s", cores=O.num_threads(), kind="oracle",
                 sample=f"FP64 push of the slots of the first {na} atoms ({int(s2)} electron-steps, "
-                       f"{t2:.1f} s) with the GPU's birth times; order-5 field, same laser")
+                       f"{t2:.1f} s), atoms and birth times from the oracle's own sampling and "
+                       f"ionization; order-5 field, same laser")
 
 
 def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk):

@@ -134,6 +134,15 @@ rpdla_status rpdla_sample_atoms(uint64_t seed, uint32_t cfg_id, uint64_t first_a
                                 int64_t n_atoms, double r_max, double z_half,
                                 double* x, double* y, double* z, void* stream);
 
+/* Hollow / annular variant (Sec. 2.2, Fig. 8: ions uniform on the surface of
+ * a hollow cylinder of radius 0..4 um): r uniform in area between r_in and
+ * r_out, r = r_out exactly when r_in == r_out; same random streams as
+ * rpdla_sample_atoms.  EINVAL unless 0 <= r_in <= r_out, z_half >= 0. */
+rpdla_status rpdla_sample_atoms_annulus(uint64_t seed, uint32_t cfg_id, uint64_t first_atom,
+                                        int64_t n_atoms, double r_in, double r_out,
+                                        double z_half, double* x, double* y, double* z,
+                                        void* stream);
+
 /* ------------------------------------------------------------------------
  * Ionization times (Sec. 2.1 "Ionization": charge states freed one after
  * another, t0 the birth time).  For atom i (index first_atom + j, position
@@ -152,6 +161,20 @@ rpdla_status rpdla_ionize(const rpdla_laser* L, uint64_t seed, uint32_t cfg_id,
                           uint64_t first_atom, int64_t n_atoms, const double* x,
                           const double* y, const double* z, int32_t k_first,
                           int32_t k_last, double* t_birth, void* stream);
+
+/* Laser phase and radius at each birth (Sec. 2.2, Figs. 6, 13, 14: the phase
+ * of the laser coincident with the birth and the distance of the parent ion
+ * from the axis), using the phase defined under Eq. (2):
+ * k z - omega t - 2 atan(z/z_r) + z r^2 / (z_r w0^2 f^2) + phi0_paper, with
+ * phi0_paper = -L->phi0, reduced to [0, 2 pi).  Slot s belongs to atom
+ * s / slots_per_atom (positions x, y, z [m], device double[n_atoms]); t_birth
+ * as from rpdla_ionize.  phase: device double[n_slots] out; r_birth: device
+ * double[n_slots] out [m] or NULL; both NaN for unborn slots.  EINVAL: bad
+ * laser, n_slots < 0, slots_per_atom < 1, null pointers with n_slots > 0. */
+rpdla_status rpdla_birth_phase(const rpdla_laser* L, int64_t n_slots, const double* t_birth,
+                               const double* x, const double* y, const double* z,
+                               int32_t slots_per_atom, double* phase, double* r_birth,
+                               void* stream);
 
 /* ------------------------------------------------------------------------
  * Push (Eqs. (7)-(14), radiation reaction dropped as in the paper below
@@ -201,6 +224,25 @@ rpdla_status rpdla_epilogue(int64_t n, const double* ux, const double* uy, const
 rpdla_status rpdla_histogram(int64_t n_slots, const double* t_birth, const double* ux,
                              const double* uy, const double* uz, const rpdla_hist_spec* spec,
                              uint64_t* counts, uint64_t* tallies, void* stream);
+
+/* Two-dimensional histogram of pairs (a[i], b[i]) split by the direction of
+ * final motion: the birth phase x birth radius maps of forward and backward
+ * electrons (Sec. 2.2, Figs. 13, 14) or a birth variable against the final
+ * energy (Fig. 6).  Pair i adds 1 at counts[dir][ia][ib], dir 0 if uz[i] > 0
+ * else 1, ia = floor((a - a_lo) / ((a_hi - a_lo) / na)), ib likewise, each
+ * bin half-open [lo, lo + width); tallies[0] counts pairs outside either range,
+ * tallies[1] pairs with a NaN in a, b or uz (unborn slots).  a, b, uz: device
+ * double[n]; counts: device uint64[2 * na * nb], tallies: device uint64[2],
+ * both ACCUMULATED into.  EINVAL: na, nb < 1, lo >= hi or non-finite, null
+ * pointers; ERANGE: na * nb > 2^28. */
+typedef struct {
+    int32_t na, nb;
+    double a_lo, a_hi, b_lo, b_hi;
+} rpdla_hist2d_spec;
+
+rpdla_status rpdla_histogram2d(int64_t n, const double* a, const double* b, const double* uz,
+                               const rpdla_hist2d_spec* spec, uint64_t* counts, uint64_t* tallies,
+                               void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched sweep: n_cfg laser configurations (host array cfgs[n_cfg]), each

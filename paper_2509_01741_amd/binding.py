@@ -54,6 +54,11 @@ class rpdla_hist_spec(C.Structure):
                 ("logE_max_MeV", C.c_double), ("angle", C.c_int32)]
 
 
+class rpdla_hist2d_spec(C.Structure):
+    _fields_ = [("na", C.c_int32), ("nb", C.c_int32), ("a_lo", C.c_double), ("a_hi", C.c_double),
+                ("b_lo", C.c_double), ("b_hi", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -69,6 +74,9 @@ def _load():
         "rpdla_rayleigh": (d, [LP]),
         "rpdla_sample_atoms": (i32, [u64, u32, u64, i64, d, d, vp, vp, vp, vp]),
         "rpdla_ionize": (i32, [LP, u64, u32, u64, i64, vp, vp, vp, i32, i32, vp, vp]),
+        "rpdla_sample_atoms_annulus": (i32, [u64, u32, u64, i64, d, d, d, vp, vp, vp, vp]),
+        "rpdla_birth_phase": (i32, [LP, i64, vp, vp, vp, vp, i32, vp, vp, vp]),
+        "rpdla_histogram2d": (i32, [i64, vp, vp, vp, C.POINTER(rpdla_hist2d_spec), vp, vp, vp]),
         "rpdla_push": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
         "rpdla_epilogue": (i32, [i64, vp, vp, vp, vp, vp, vp, vp, vp]),
@@ -150,6 +158,50 @@ def rpdla_sample_atoms(seed, cfg_id, first_atom, n_atoms, r_max, z_half, x=None,
                                   _dev(x, "x", n_atoms), _dev(y, "y", n_atoms),
                                   _dev(z, "z", n_atoms), _stream(stream)), "rpdla_sample_atoms")
     return x, y, z
+
+
+def rpdla_sample_atoms_annulus(seed, cfg_id, first_atom, n_atoms, r_in, r_out, z_half, x=None,
+                               y=None, z=None, stream=None, device=None):
+    x = _empty(n_atoms, device=device) if x is None else x
+    y = _empty(n_atoms, like=x) if y is None else y
+    z = _empty(n_atoms, like=x) if z is None else z
+    _check(lib.rpdla_sample_atoms_annulus(seed, cfg_id, first_atom, n_atoms, r_in, r_out, z_half,
+                                          _dev(x, "x", n_atoms), _dev(y, "y", n_atoms),
+                                          _dev(z, "z", n_atoms), _stream(stream)),
+           "rpdla_sample_atoms_annulus")
+    return x, y, z
+
+
+def rpdla_birth_phase(L, t_birth, x, y, z, slots_per_atom, phase=None, r_birth=None,
+                      want_radius=True, stream=None):
+    """Returns (phase, r_birth); r_birth is None when want_radius is False."""
+    n = t_birth.numel()
+    na = (n + slots_per_atom - 1) // slots_per_atom
+    phase = _empty(n, like=t_birth) if phase is None else phase
+    if want_radius and r_birth is None:
+        r_birth = _empty(n, like=t_birth)
+    rp = _dev(r_birth, "r_birth", n) if r_birth is not None else None
+    _check(lib.rpdla_birth_phase(C.byref(L), n, _dev(t_birth, "t_birth", n), _dev(x, "x", na),
+                                 _dev(y, "y", na), _dev(z, "z", na), slots_per_atom,
+                                 _dev(phase, "phase", n), rp, _stream(stream)),
+           "rpdla_birth_phase")
+    return phase, r_birth
+
+
+def rpdla_histogram2d(a, b, uz, spec, counts=None, tallies=None, stream=None):
+    """counts: int64 tensor [2, na, nb] and tallies: int64 tensor [2] (the
+    library adds unsigned 64-bit counts into them)."""
+    n = a.numel()
+    nbins = 2 * spec.na * spec.nb
+    if counts is None:
+        counts = torch.zeros((2, spec.na, spec.nb), dtype=torch.int64, device=a.device)
+    if tallies is None:
+        tallies = torch.zeros(2, dtype=torch.int64, device=a.device)
+    _check(lib.rpdla_histogram2d(n, _dev(a, "a", n), _dev(b, "b", n), _dev(uz, "uz", n),
+                                 C.byref(spec), _dev(counts, "counts", nbins, torch.int64),
+                                 _dev(tallies, "tallies", 2, torch.int64), _stream(stream)),
+           "rpdla_histogram2d")
+    return counts, tallies
 
 
 def rpdla_ionize(L, seed, cfg_id, first_atom, x, y, z, k_first, k_last, t_birth=None, stream=None):

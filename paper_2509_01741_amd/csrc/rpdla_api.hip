@@ -297,6 +297,41 @@ rpdla_status rpdla_sample_atoms(uint64_t seed, uint32_t cfg_id, uint64_t first_a
     return RPDLA_OK;
 }
 
+rpdla_status rpdla_sample_atoms_annulus(uint64_t seed, uint32_t cfg_id, uint64_t first_atom,
+                                        int64_t n, double r_in, double r_out, double z_half,
+                                        double* x, double* y, double* z, void* stream)
+{
+    if (n < 0) return fail(RPDLA_EINVAL, "n_atoms < 0");
+    if (!(is_fin(r_in) && is_fin(r_out) && is_fin(z_half) && r_in >= 0 && r_out >= r_in && z_half >= 0))
+        return fail(RPDLA_EINVAL, "need 0 <= r_in <= r_out and z_half >= 0, finite");
+    if (n == 0) return RPDLA_OK;
+    if (!x || !y || !z) return fail(RPDLA_EINVAL, "null output pointer");
+    if (n > ((int64_t)1 << 40)) return fail(RPDLA_ERANGE, "n_atoms too large");
+    hipLaunchKernelGGL(rpdla::sample_annulus_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0,
+                       (hipStream_t)stream, seed, cfg_id, first_atom, n, r_in, r_out, z_half, x, y, z);
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_birth_phase(const rpdla_laser* L, int64_t n_slots, const double* t_birth,
+                               const double* x, const double* y, const double* z,
+                               int32_t slots_per_atom, double* phase, double* r_birth,
+                               void* stream)
+{
+    rpdla_status st = check_laser(L);
+    if (st != RPDLA_OK) return st;
+    if (n_slots < 0) return fail(RPDLA_EINVAL, "n_slots < 0");
+    if (slots_per_atom < 1) return fail(RPDLA_EINVAL, "slots_per_atom < 1");
+    if (n_slots == 0) return RPDLA_OK;
+    if (!t_birth || !x || !y || !z || !phase) return fail(RPDLA_EINVAL, "null pointer");
+    const DevCfg c = make_cfg(L);
+    hipLaunchKernelGGL(rpdla::birth_phase_kernel, dim3((unsigned)cdiv(n_slots, 256)), dim3(256), 0,
+                       (hipStream_t)stream, c, n_slots, t_birth, x, y, z, slots_per_atom, phase,
+                       r_birth);
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
 rpdla_status rpdla_ionize(const rpdla_laser* L, uint64_t seed, uint32_t cfg_id, uint64_t first_atom,
                           int64_t n, const double* x, const double* y, const double* z,
                           int32_t k_first, int32_t k_last, double* t_birth, void* stream)
@@ -763,6 +798,36 @@ rpdla_status rpdla_autotune(const rpdla_laser* L, int32_t precision, int64_t n_a
         memcpy(report, js.data(), m);
         report[m] = 0;
     }
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_histogram2d(int64_t n, const double* a, const double* b, const double* uz,
+                               const rpdla_hist2d_spec* spec, uint64_t* counts, uint64_t* tallies,
+                               void* stream)
+{
+    if (!spec) return fail(RPDLA_EINVAL, "spec is NULL");
+    if (spec->na < 1 || spec->nb < 1) return fail(RPDLA_EINVAL, "na, nb must be >= 1");
+    if (!(is_fin(spec->a_lo) && is_fin(spec->a_hi) && spec->a_lo < spec->a_hi &&
+          is_fin(spec->b_lo) && is_fin(spec->b_hi) && spec->b_lo < spec->b_hi))
+        return fail(RPDLA_EINVAL, "need finite a_lo < a_hi and b_lo < b_hi");
+    if ((int64_t)spec->na * spec->nb > ((int64_t)1 << 28)) return fail(RPDLA_ERANGE, "too many bins");
+    if (n < 0) return fail(RPDLA_EINVAL, "n < 0");
+    if (!counts || !tallies) return fail(RPDLA_EINVAL, "null output pointer");
+    if (n == 0) return RPDLA_OK;
+    if (!a || !b || !uz) return fail(RPDLA_EINVAL, "null input pointer");
+    rpdla::Hist2dArgs H;
+    H.a_lo = spec->a_lo;
+    H.wa = (spec->a_hi - spec->a_lo) / (double)spec->na;
+    H.b_lo = spec->b_lo;
+    H.wb = (spec->b_hi - spec->b_lo) / (double)spec->nb;
+    H.na = spec->na;
+    H.nb = spec->nb;
+    int64_t blocks = cdiv(n, 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(rpdla::histogram2d_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, H, n, a, b, uz, (unsigned long long*)counts,
+                       (unsigned long long*)tallies);
+    RPDLA_HIP(hipGetLastError());
     return RPDLA_OK;
 }
 

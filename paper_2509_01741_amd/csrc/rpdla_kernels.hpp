@@ -29,6 +29,50 @@ __global__ void __launch_bounds__(256) sample_atoms_kernel(
     z[i] = z_half * (2.0 * u01(r.v[2]) - 1.0);
 }
 
+// Annulus: r uniform in area between r_in and r_out (r = r_out exactly when
+// r_in == r_out, a hollow-cylinder surface), azimuth and z as above.
+__global__ void __launch_bounds__(256) sample_annulus_kernel(
+    uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n, double r_in, double r_out,
+    double z_half, double* __restrict__ x, double* __restrict__ y, double* __restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const U64x4 r = philox4x64(first_atom + (uint64_t)i, 0, 0, 0, seed, (uint64_t)cfg);
+    const double rad = (r_in == r_out) ? r_out
+                                        : sqrt(r_in * r_in + u01(r.v[0]) * (r_out * r_out - r_in * r_in));
+    double sn, cs;
+    sincos(kTwoPi * u01(r.v[1]), &sn, &cs);
+    x[i] = rad * cs;
+    y[i] = rad * sn;
+    z[i] = z_half * (2.0 * u01(r.v[2]) - 1.0);
+}
+
+// Laser phase at each birth, the phase defined under Eq. (2) of the paper
+// (k z - omega t - 2 atan(z/z_r) + z r^2/(z_r w0^2 f^2), with the paper's
+// carrier phase equal to minus this library's), in [0, 2 pi), and the radius
+// of the parent ion (optional); NaN for unborn slots.
+__global__ void __launch_bounds__(256) birth_phase_kernel(
+    DevCfg c, int64_t n, const double* __restrict__ tb, const double* __restrict__ x,
+    const double* __restrict__ y, const double* __restrict__ z, int spa,
+    double* __restrict__ phase, double* __restrict__ r_birth)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double t = tb[s];
+    const int64_t a = s / spa;
+    const bool born = t < __builtin_inf();
+    if (r_birth) r_birth[s] = born ? sqrt(x[a] * x[a] + y[a] * y[a]) : __builtin_nan("");
+    if (!born) { phase[s] = __builtin_nan(""); return; }
+    const double X = x[a] * c.k, Y = y[a] * c.k, Z = z[a] * c.k;
+    const double rho2 = (X * X + Y * Y) * c.inv_w0n2;
+    const double zeta = Z * c.inv_zrn;
+    double ph = Z - t * c.omega - 2.0 * atan(zeta) + zeta * rho2 / (1.0 + zeta * zeta) - c.phi0;
+    ph = fmod(ph, kTwoPi);
+    if (ph < 0.0) ph += kTwoPi;
+    if (ph >= kTwoPi) ph -= kTwoPi;
+    phase[s] = ph;
+}
+
 // ---------------------------------------------------------------------------
 // Ionization.  One lane per atom.  Time axis in panels of width h from the
 // window start; state s (charge state k_first + s) accumulates GL-4 panel
@@ -567,6 +611,49 @@ __global__ void __launch_bounds__(256) histogram_kernel(
         int tally = -1, dir = -1;
         if (i < n) key = bin_key(H, tb[i], ux[i], uy[i], uz[i], tally, dir);
         wave_hist_commit(key, tally, dir, counts, tallies);
+    }
+}
+
+// Two-dimensional forward/backward histogram: pair i adds 1 at
+// counts[dir][ia][ib], dir 0 if uz > 0 else 1, ia = floor((a - a_lo)/wa),
+// ib likewise; tallies[0] counts pairs outside the ranges, tallies[1] pairs
+// with a NaN.  Same arithmetic, without contraction, as the definition.
+struct Hist2dArgs {
+    double a_lo, wa, b_lo, wb;
+    int32_t na, nb;
+};
+
+__global__ void __launch_bounds__(256) histogram2d_kernel(
+    Hist2dArgs H, int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+    const double* __restrict__ uz, unsigned long long* __restrict__ counts,
+    unsigned long long* __restrict__ tallies)
+{
+#pragma clang fp contract(off)
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t w = base0; w < n; w += stride) {
+        const int64_t i = w + __lane_id();
+        int64_t key = -1;
+        int tally = -1;
+        if (i < n) {
+            const double av = a[i], bv = b[i], u = uz[i];
+            if (isnan(av) || isnan(bv) || isnan(u)) {
+                tally = 1;
+            } else {
+                const double fa = floor((av - H.a_lo) / H.wa);
+                const double fb = floor((bv - H.b_lo) / H.wb);
+                if (fa >= 0.0 && fa < (double)H.na && fb >= 0.0 && fb < (double)H.nb)
+                    key = ((int64_t)(u > 0.0 ? 0 : 1) * H.na + (int64_t)fa) * H.nb + (int64_t)fb;
+                else
+                    tally = 0;
+            }
+        }
+        wave_merge_add(key, counts);
+        const uint64_t t0 = __ballot(tally == 0), t1 = __ballot(tally == 1);
+        if (__lane_id() == 0) {
+            if (t0) atomicAdd(&tallies[0], (unsigned long long)__popcll(t0));
+            if (t1) atomicAdd(&tallies[1], (unsigned long long)__popcll(t1));
+        }
     }
 }
 

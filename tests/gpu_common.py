@@ -15,13 +15,20 @@ def require_gpu():
     return torch
 
 
-def energy_parity(ux_a, uy_a, uz_a, ux_b, uy_b, uz_b, orc):
-    """Fraction of electrons whose kinetic energies agree to 1e-8 relative
-    (+1e-12 MeV) and whose forward/backward flags agree."""
-    Ka, _, _, fa = orc.epilogue(ux_a, uy_a, uz_a)
-    Kb, _, _, fb = orc.epilogue(ux_b, uy_b, uz_b)
-    ok = np.abs(Ka - Kb) <= 1e-8 * np.abs(Kb) + 1e-12
-    return ok, fa == fb, Ka, Kb
+def gpu_energy(B, torch, ux, uy, uz):
+    """Kinetic energy [MeV] and forward flag from the library's own epilogue
+    kernel, for GPU momenta (tensors or arrays)."""
+    t = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+         for a in (ux, uy, uz)]
+    K, _, _, fwd = B.rpdla_epilogue(*t)
+    return K.cpu().numpy(), fwd.cpu().numpy()
+
+
+def energy_parity(Kg, fg, Ko, fo):
+    """Per electron: energies agree to 1e-8 relative (+1e-12 MeV); directions
+    agree."""
+    ok = np.abs(Kg - Ko) <= 1e-8 * np.abs(Ko) + 1e-12
+    return ok, np.asarray(fg) == np.asarray(fo)
 
 
 def allowed_failures(n, frac=0.999):

@@ -126,3 +126,40 @@ def test_ne_table_matches_oracle(orc):
     m = re.search(r"kNeIpEv\[10\] = \{([^}]*)\}", src)
     vals = np.array([float(v) for v in m.group(1).replace("\n", " ").split(",")])
     assert np.array_equal(vals, orc.ne_ip_ev())
+
+
+def test_experiment_entry_points_validation():
+    from paper_2509_01741_amd import binding as B
+    lib = B.lib
+    L = B.rpdla_laser_init_intensity(0.8e-6, 2.5e-6, 30e-15, 5e19)
+    p = C.c_void_p(0)
+    # annulus sampler: radii order, negative n, empty call
+    assert lib.rpdla_sample_atoms_annulus(0, 0, 0, 5, 2.0, 1.0, 1.0, p, p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_sample_atoms_annulus(0, 0, 0, 5, -1.0, 1.0, 1.0, p, p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_sample_atoms_annulus(0, 0, 0, -1, 0.0, 1.0, 1.0, p, p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_sample_atoms_annulus(0, 0, 0, 5, 0.0, 1.0, 1.0, p, p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_sample_atoms_annulus(0, 0, 0, 0, 1.0, 1.0, 1.0, p, p, p, p) == B.RPDLA_OK
+    # birth phase: slots_per_atom, null pointers, empty call (r_birth may be NULL)
+    assert lib.rpdla_birth_phase(C.byref(L), 4, p, p, p, p, 0, p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_birth_phase(C.byref(L), 4, p, p, p, p, 1, p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_birth_phase(C.byref(L), 0, p, p, p, p, 1, p, p, p) == B.RPDLA_OK
+    # 2-d histogram spec
+    sp = B.rpdla_hist2d_spec(0, 4, 0.0, 1.0, 0.0, 1.0)
+    assert lib.rpdla_histogram2d(4, p, p, p, C.byref(sp), p, p, p) == B.RPDLA_EINVAL
+    sp = B.rpdla_hist2d_spec(4, 4, 1.0, 1.0, 0.0, 1.0)
+    assert lib.rpdla_histogram2d(4, p, p, p, C.byref(sp), p, p, p) == B.RPDLA_EINVAL
+    sp = B.rpdla_hist2d_spec(4, 4, 0.0, 1.0, 0.0, float("nan"))
+    assert lib.rpdla_histogram2d(4, p, p, p, C.byref(sp), p, p, p) == B.RPDLA_EINVAL
+    sp = B.rpdla_hist2d_spec(1 << 15, 1 << 14, 0.0, 1.0, 0.0, 1.0)
+    assert lib.rpdla_histogram2d(4, p, p, p, C.byref(sp), p, p, p) == B.RPDLA_ERANGE
+    sp = B.rpdla_hist2d_spec(4, 4, 0.0, 1.0, 0.0, 1.0)
+    assert lib.rpdla_histogram2d(4, p, p, p, C.byref(sp), p, p, p) == B.RPDLA_EINVAL
+    assert lib.rpdla_histogram2d(0, p, p, p, C.byref(sp), C.c_void_p(256), C.c_void_p(256),
+                                 p) == B.RPDLA_OK
+
+
+def test_hist2d_spec_layout():
+    # the ctypes mirror must match the C struct: int32 na, nb then four doubles
+    from paper_2509_01741_amd import binding as B
+    assert C.sizeof(B.rpdla_hist2d_spec) == 40
+    assert B.rpdla_hist2d_spec.a_lo.offset == 8 and B.rpdla_hist2d_spec.b_hi.offset == 32
