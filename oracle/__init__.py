@@ -98,6 +98,12 @@ def lib():
                                             C.c_double, C.c_double, C.c_double, _D, _D, _D]),
         "orc_histogram2d": (None, [C.c_int64, _D, _D, _D, C.c_int32, C.c_double, C.c_double,
                                    C.c_int32, C.c_double, C.c_double, _U64, _U64]),
+        "orc_critical_field": (C.c_double, []),
+        "orc_rr_terms": (None, [LP, C.c_double, _D, _D, _D]),
+        "orc_push_one_rr": (None, [LP, C.c_int, C.c_double, C.c_double, C.c_double, _D, _D, _D,
+                                   _D, _D]),
+        "orc_push_rr": (None, [LP, C.c_int, C.c_int64, _D, _D, _D, _D, C.c_int, _D, _D, _D, _D,
+                               _D, _D, _D]),
         "orc_ne_ip_table": (C.POINTER(C.c_double), []),
     }
     for name, (res, args) in sig.items():
@@ -270,6 +276,38 @@ def histogram2d(a, b, uz, na, a_lo, a_hi, nb, b_lo, b_hi):
     tallies = np.zeros(2, dtype=np.uint64)
     lib().orc_histogram2d(a.size, a, b, uz, na, a_lo, a_hi, nb, b_lo, b_hi, counts, tallies)
     return counts, tallies
+
+
+def critical_field() -> float:
+    """E_cr = m^2 c^3 / (e hbar) [V/m]."""
+    return lib().orc_critical_field()
+
+
+def rr_terms(L: Laser, t, Y):
+    """Radiation-reaction du/dt (u = p/mc) of Eq. (3) and chi, for state
+    Y = (x, y, z, ux, uy, uz) at time t."""
+    du = np.zeros(3)
+    chi = np.zeros(1)
+    lib().orc_rr_terms(C.byref(L), float(t), _d(Y), du, chi)
+    return du, float(chi[0])
+
+
+def push_one_rr(L: Laser, rr, t0, t_end, h, x0, u0):
+    """One electron with initial momentum u0: (xf, uf, chi_max)."""
+    xf, uf, cm = np.zeros(3), np.zeros(3), np.zeros(1)
+    lib().orc_push_one_rr(C.byref(L), int(rr), t0, t_end, h, _d(x0), _d(u0), xf, uf, cm)
+    return xf, uf, float(cm[0])
+
+
+def push_rr(L: Laser, rr, t_birth, x0, y0, z0, slots_per_atom):
+    """Like push() with Eq. (3)'s radiation term on (rr=1) or off, plus the
+    per-electron maximum of chi: (ux, uy, uz, xf, yf, zf, chi_max)."""
+    t_birth = _d(t_birth)
+    n = t_birth.size
+    out = [np.zeros(n) for _ in range(7)]
+    lib().orc_push_rr(C.byref(L), int(rr), n, t_birth, _d(x0), _d(y0), _d(z0), slots_per_atom,
+                      *out)
+    return tuple(out)
 
 
 def num_threads() -> int:

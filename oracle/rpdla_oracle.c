@@ -45,6 +45,8 @@
 #define ORC_TAUA     2.4188843265857e-17    /* atomic unit of time, s         */
 #define ORC_EH_EV    27.211386245988        /* Hartree energy, eV             */
 #define ORC_PI       3.14159265358979323846
+#define ORC_HBAR     1.054571817e-34        /* reduced Planck constant, J s   */
+#define ORC_ALPHA    7.2973525693e-3        /* fine-structure constant        */
 
 /* Neon ionization potentials Ne^(k-1)+ -> Ne^k+, k = 1..10, in eV (NIST ASD
  * values; the paper names the charge states but prints no potentials). */
@@ -684,5 +686,111 @@ void orc_histogram2d(int64_t n, const double* a, const double* b, const double* 
         }
         const int dir = (uz[i] > 0.0) ? 0 : 1;
         counts[((int64_t)dir * na + (int64_t)fa) * nb + (int64_t)fb] += 1;
+    }
+}
+
+
+/* ---------------------------------------------------------------------------
+ * Radiation reaction and the quantum parameter (Sec. 2.1, Eqs. (3)-(6)).
+ *
+ * Eq. (3) adds to the Lorentz force the leading (gamma^2) term of the
+ * Landau-Lifshitz force.  In SI units
+ *   F_RR = -(e^4 gamma^2 / (6 pi eps0 m^2 c^5)) v [(E + v x B)^2 - (v.E)^2 / c^2].
+ * Reading: the printed coefficient 2 e^4 gamma^2 / (3 m c^5) is the Gaussian
+ * one with a power of m lost; with e^2 -> e^2/(4 pi eps0) and B -> c B it
+ * becomes the SI coefficient above.  The other Landau-Lifshitz terms (field
+ * derivatives, gamma^0) are not in Eq. (3) and are not added.
+ *
+ * Quantum parameter: the general form of Eq. (4) for an electron of any
+ * velocity, chi = (gamma / E_cr) sqrt((E + v x B)^2 - (v.E)^2 / c^2),
+ * E_cr = m^2 c^3 / (e hbar); at rest it is E / E_cr (Eq. (5)) and head-on
+ * against a plane wave gamma (1 + beta) E / E_cr (Eq. (4)).  The classical
+ * radiation parameter of Eq. (6) is Rc = alpha a0 chi with a0 = e E0/(m c
+ * omega) the laser's normalized amplitude.
+ *
+ * orc_push_rr pushes like orc_push with the term of Eq. (3) switched on
+ * (rr = 1) or off (rr = 0) and records, per electron, the largest chi met at
+ * the start of its RK4 steps (0 if it takes none).
+ * ------------------------------------------------------------------------- */
+double orc_critical_field(void)
+{
+    return ORC_ME * ORC_ME * ORC_C * ORC_C * ORC_C / (ORC_QE * ORC_HBAR);
+}
+
+/* du/dt of Eq. (3)'s radiation term (u = p / m c) and chi, for state Y at t. */
+void orc_rr_terms(const orc_laser* L, double t, const double Y[6], double duRR[3], double* chi)
+{
+    double E[3], B[3];
+    orc_field(L, Y[0], Y[1], Y[2], t, E, B);
+    const double gam = sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
+    const double v[3] = {ORC_C * Y[3] / gam, ORC_C * Y[4] / gam, ORC_C * Y[5] / gam};
+    const double f[3] = {E[0] + (v[1] * B[2] - v[2] * B[1]),
+                         E[1] + (v[2] * B[0] - v[0] * B[2]),
+                         E[2] + (v[0] * B[1] - v[1] * B[0])};
+    const double vE = (v[0] * E[0] + v[1] * E[1] + v[2] * E[2]) / ORC_C;
+    double Q = f[0] * f[0] + f[1] * f[1] + f[2] * f[2] - vE * vE;
+    if (Q < 0.0) Q = 0.0;
+    const double e2 = ORC_QE * ORC_QE;
+    const double coef = e2 * e2 * gam * gam /
+                        (6.0 * ORC_PI * ORC_EPS0 * ORC_ME * ORC_ME * ORC_C * ORC_C * ORC_C * ORC_C * ORC_C);
+    for (int i = 0; i < 3; ++i) duRR[i] = -coef * v[i] * Q / (ORC_ME * ORC_C);
+    *chi = gam * sqrt(Q) / orc_critical_field();
+}
+
+static void orc_rhs_rr(const orc_laser* L, int rr, double t, const double Y[6], double dY[6],
+                       double* chi)
+{
+    double du[3];
+    orc_rhs(L, t, Y, dY);
+    orc_rr_terms(L, t, Y, du, chi);
+    if (rr)
+        for (int i = 0; i < 3; ++i) dY[3 + i] += du[i];
+}
+
+void orc_push_one_rr(const orc_laser* L, int rr, double t0, double t_end, double h,
+                     const double x0[3], const double u0[3], double xf[3], double uf[3],
+                     double* chi_max)
+{
+    double Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
+    double cm = 0.0;
+    const int64_t N = (int64_t)ceil((t_end - t0) / h);
+    for (int64_t n = 0; n < N; ++n) {
+        double ta = t0 + (double)n * h;
+        double hn = (n == N - 1) ? t_end - ta : h;
+        double k1[6], k2[6], k3[6], k4[6], Yt[6], chi, dummy;
+        orc_rhs_rr(L, rr, ta, Y, k1, &chi);
+        if (chi > cm) cm = chi;
+        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];
+        orc_rhs_rr(L, rr, ta + 0.5 * hn, Yt, k2, &dummy);
+        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k2[i];
+        orc_rhs_rr(L, rr, ta + 0.5 * hn, Yt, k3, &dummy);
+        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + hn * k3[i];
+        orc_rhs_rr(L, rr, ta + hn, Yt, k4, &dummy);
+        for (int i = 0; i < 6; ++i)
+            Y[i] += hn / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    }
+    for (int i = 0; i < 3; ++i) { xf[i] = Y[i]; uf[i] = Y[3 + i]; }
+    *chi_max = cm;
+}
+
+void orc_push_rr(const orc_laser* L, int rr, int64_t n_slots, const double* t_birth,
+                 const double* x0, const double* y0, const double* z0, int slots_per_atom,
+                 double* ux, double* uy, double* uz, double* xf, double* yf, double* zf,
+                 double* chi_max)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_slots; ++s) {
+        int64_t a = s / slots_per_atom;
+        double t0 = t_birth[s];
+        double ts, te;
+        orc_window(L, z0[a], &ts, &te);
+        if (!(t0 < INFINITY) || !(t0 >= ts - L->dt)) {
+            ux[s] = uy[s] = uz[s] = xf[s] = yf[s] = zf[s] = chi_max[s] = NAN;
+            continue;
+        }
+        double X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
+        orc_push_one_rr(L, rr, t0, te, L->dt, X0, U0, XF, UF, &chi_max[s]);
+        ux[s] = UF[0]; uy[s] = UF[1]; uz[s] = UF[2];
+        xf[s] = XF[0]; yf[s] = XF[1]; zf[s] = XF[2];
     }
 }
