@@ -201,6 +201,30 @@ rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots
                         double* uz, double* xf, double* yf, double* zf, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Push with the radiation term of Eq. (3) and the quantum parameter of
+ * Eqs. (4)-(6) (Sec. 2.1).  Same slots, window, RK4 steps and outputs as
+ * rpdla_push in RPDLA_FP64, with
+ *   radiation_reaction = 1: the gamma^2 Landau-Lifshitz term added to the
+ *     Lorentz force, -(e^4 gamma^2 / (6 pi eps0 m^2 c^5)) v [(E + v x B)^2 -
+ *     (v.E)^2/c^2] (SI form of Eq. (3), whose printed coefficient is read as
+ *     the Gaussian 2 e^4 gamma^2 / (3 m^2 c^5));
+ *   radiation_reaction = 0: the plain Lorentz force.
+ * chi_max: device double[n_slots] out, or NULL: per electron the largest
+ * chi = (gamma / E_cr) sqrt((E + v x B)^2 - (v.E)^2/c^2), E_cr = m^2 c^3 /
+ * (e hbar), over the starts of its RK4 steps (0 if it takes none, NaN for
+ * unborn and invalid slots).  The classical radiation parameter of Eq. (6)
+ * is Rc = alpha a0 chi, a0 = e A / (m c omega).
+ * EINVAL: bad laser, radiation_reaction not 0 or 1, n_slots < 0,
+ * slots_per_atom < 1, null pointers (other than chi_max) with n_slots > 0.
+ * Uses a small stream-ordered device allocation for its work queue.
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_push_rr(const rpdla_laser* L, int32_t radiation_reaction, int64_t n_slots,
+                           const double* t_birth, const double* x0, const double* y0,
+                           const double* z0, int32_t slots_per_atom, double* ux, double* uy,
+                           double* uz, double* xf, double* yf, double* zf, double* chi_max,
+                           void* stream);
+
+/* ------------------------------------------------------------------------
  * Per-electron outputs (text after Eq. (14); Sec. 2.2, Fig. 5): kinetic
  * energy K = m c^2 u^2 / (gamma + 1) [MeV] (= (gamma - 1) m c^2 without
  * cancellation), polar emission angle theta = atan2(|u_perp|, u_z), azimuth

@@ -76,6 +76,8 @@ def _load():
         "rpdla_ionize": (i32, [LP, u64, u32, u64, i64, vp, vp, vp, i32, i32, vp, vp]),
         "rpdla_sample_atoms_annulus": (i32, [u64, u32, u64, i64, d, d, d, vp, vp, vp, vp]),
         "rpdla_birth_phase": (i32, [LP, i64, vp, vp, vp, vp, i32, vp, vp, vp]),
+        "rpdla_push_rr": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                                vp]),
         "rpdla_histogram2d": (i32, [i64, vp, vp, vp, C.POINTER(rpdla_hist2d_spec), vp, vp, vp]),
         "rpdla_push": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
@@ -226,6 +228,26 @@ def rpdla_push(L, precision, t_birth, x0, y0, z0, slots_per_atom, out=None, stre
                           _dev(xf, "xf", n), _dev(yf, "yf", n), _dev(zf, "zf", n),
                           _stream(stream)), "rpdla_push")
     return out
+
+
+def rpdla_push_rr(L, radiation_reaction, t_birth, x0, y0, z0, slots_per_atom, out=None,
+                  chi_max=None, want_chi=True, stream=None):
+    """FP64 push with Eq. (3)'s radiation term on (1) or off (0); returns
+    (ux, uy, uz, xf, yf, zf, chi_max), chi_max None when want_chi is False."""
+    n = t_birth.numel()
+    na = (n + slots_per_atom - 1) // slots_per_atom
+    if out is None:
+        out = tuple(_empty(n, like=t_birth) for _ in range(6))
+    if want_chi and chi_max is None:
+        chi_max = _empty(n, like=t_birth)
+    ux, uy, uz, xf, yf, zf = out
+    cp = _dev(chi_max, "chi_max", n) if chi_max is not None else None
+    _check(lib.rpdla_push_rr(C.byref(L), int(radiation_reaction), n, _dev(t_birth, "t_birth", n),
+                             _dev(x0, "x0", na), _dev(y0, "y0", na), _dev(z0, "z0", na),
+                             slots_per_atom, _dev(ux, "ux", n), _dev(uy, "uy", n),
+                             _dev(uz, "uz", n), _dev(xf, "xf", n), _dev(yf, "yf", n),
+                             _dev(zf, "zf", n), cp, _stream(stream)), "rpdla_push_rr")
+    return tuple(out) + (chi_max,)
 
 
 def rpdla_epilogue(ux, uy, uz, out=None, stream=None):

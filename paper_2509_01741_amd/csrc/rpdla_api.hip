@@ -33,6 +33,7 @@ constexpr double kEa = 5.14220674763e11;       // atomic unit of field [V/m]
 constexpr double kTauA = 2.4188843265857e-17;  // atomic unit of time [s]
 constexpr double kEhEv = 27.211386245988;      // Hartree [eV]
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kHbar = 1.054571817e-34;        // reduced Planck constant [J s]
 
 // Neon ionization potentials Ne^(k-1)+ -> Ne^k+ [eV] (NIST ASD).
 constexpr double kNeIpEv[10] = {21.564540, 40.96297, 63.4233, 97.1900, 126.247,
@@ -149,6 +150,9 @@ DevCfg make_cfg(const rpdla_laser* L)
     const double wa = (18.0 + sqrt(30.0)) / 36.0, wb = (18.0 - sqrt(30.0)) / 36.0;
     c.gl_x[0] = -gb; c.gl_x[1] = -ga; c.gl_x[2] = ga; c.gl_x[3] = gb;
     c.gl_w[0] = wb; c.gl_w[1] = wa; c.gl_w[2] = wa; c.gl_w[3] = wb;
+    const double re = kQe * kQe / (4.0 * kPi * kEps0 * kMe * kC * kC);   // classical radius
+    c.rr_kappa = 2.0 / 3.0 * k * re;
+    c.chi_eta = kHbar * om / (kMe * kC * kC);
     return c;
 }
 
@@ -220,6 +224,23 @@ rpdla_status launch_push(const DevCfg& c, int prec, const rpdla::PushIO& io, hip
         hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
     } else {
         auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecMixed>;
+        const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
+    }
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
+template <int FIELD>
+rpdla_status launch_push_rr(const DevCfg& c, bool rr, const rpdla::PushIO& io, hipStream_t st)
+{
+    const Shape sh = get_shape(kKindPush, FIELD, RPDLA_FP64);
+    if (rr) {
+        auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecRR<true>>;
+        const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
+    } else {
+        auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecRR<false>>;
         const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
         hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
     }
@@ -382,6 +403,43 @@ rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots
     case 5: st = launch_push<5>(c, precision, io, s); break;
     case 10: st = launch_push<10>(c, precision, io, s); break;
     default: st = launch_push<11>(c, precision, io, s); break;
+    }
+    hipError_t fe = hipFreeAsync(q, s);
+    if (st != RPDLA_OK) return st;
+    if (fe != hipSuccess) return fail(RPDLA_EHIP, "hipFreeAsync: %s", hipGetErrorString(fe));
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_push_rr(const rpdla_laser* L, int32_t radiation_reaction, int64_t n_slots,
+                           const double* t_birth, const double* x0, const double* y0,
+                           const double* z0, int32_t slots_per_atom, double* ux, double* uy,
+                           double* uz, double* xf, double* yf, double* zf, double* chi_max,
+                           void* stream)
+{
+    rpdla_status st = check_laser(L);
+    if (st != RPDLA_OK) return st;
+    if (radiation_reaction != 0 && radiation_reaction != 1)
+        return fail(RPDLA_EINVAL, "radiation_reaction must be 0 or 1");
+    if (n_slots < 0) return fail(RPDLA_EINVAL, "n_slots < 0");
+    if (slots_per_atom < 1) return fail(RPDLA_EINVAL, "slots_per_atom < 1");
+    if (n_slots == 0) return RPDLA_OK;
+    if (!t_birth || !x0 || !y0 || !z0 || !ux || !uy || !uz || !xf || !yf || !zf)
+        return fail(RPDLA_EINVAL, "null pointer");
+    if (n_slots > ((int64_t)1 << 40)) return fail(RPDLA_ERANGE, "n_slots too large");
+    const DevCfg c = make_cfg(L);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* q = nullptr;
+    RPDLA_HIP(hipMallocAsync((void**)&q, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(64), 0, s, q, (int64_t)1);
+    rpdla::PushIO io{t_birth, x0, y0, z0, slots_per_atom, n_slots, ux, uy, uz, xf, yf, zf, q,
+                     chi_max};
+    const bool rr = radiation_reaction == 1;
+    switch (L->field) {
+    case 1: st = launch_push_rr<1>(c, rr, io, s); break;
+    case 3: st = launch_push_rr<3>(c, rr, io, s); break;
+    case 5: st = launch_push_rr<5>(c, rr, io, s); break;
+    case 10: st = launch_push_rr<10>(c, rr, io, s); break;
+    default: st = launch_push_rr<11>(c, rr, io, s); break;
     }
     hipError_t fe = hipFreeAsync(q, s);
     if (st != RPDLA_OK) return st;

@@ -40,6 +40,8 @@ struct DevCfg {
     double adk_a2thr[kMaxStates];  // |a|^2 below which ln w < lnw_zero - 5 (exact skip)
     double lnw_zero;
     double gl_x[4], gl_w[4];       // Gauss-Legendre 4-point nodes / weights on [-1, 1]
+    double rr_kappa;               // (2/3) k r_e: Landau-Lifshitz gamma^2 term, normalized
+    double chi_eta;                // hbar omega / (m c^2): chi = eta gamma sqrt(Q)
 };
 
 // The subset of DevCfg the push needs (staged in LDS by the batched push).

@@ -302,6 +302,89 @@ __device__ inline void elec_final(const CFG& c, const ElecF64& e, double& ux, do
 }
 
 // ---------------------------------------------------------------------------
+// Radiation reaction (Eq. (3)) and the quantum parameter (Eqs. (4)-(5)).  In
+// normalized units the gamma^2 Landau-Lifshitz term is
+//   du/dtau = -kappa gamma u Q,   Q = (a + beta x b)^2 - (beta . a)^2,
+// kappa = (2/3) k r_e, and chi = eta gamma sqrt(Q), eta = hbar omega/(m c^2).
+// ElecRR<RR> pushes with the term on (RR) or off and keeps the largest
+// gamma^2 Q met at its step starts (chi^2 / eta^2).
+// ---------------------------------------------------------------------------
+template <bool RR>
+struct ElecRR : ElecF64 {
+    double g2q;
+};
+
+// Right-hand side with the radiation term; returns gamma^2 Q at the state.
+template <int FIELD, bool RR, class CFG>
+__device__ inline double rhs_rr_f64(const CFG& c, double tau, double X, double Y, double Z,
+                                    double ux, double uy, double uz, double& dX, double& dY,
+                                    double& dZ, double& dux, double& duy, double& duz)
+{
+    double ax, ay, az, bx, by, bz;
+    field_f64<FIELD, true, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
+    const double ig = fm::rsqrt_ge1_f64(1.0 + ux * ux + uy * uy + uz * uz);
+    dX = ux * ig; dY = uy * ig; dZ = uz * ig;
+    const double fx = ax + (dY * bz - dZ * by);
+    const double fy = ay + (dZ * bx - dX * bz);
+    const double fz = az + (dX * by - dY * bx);
+    const double ba = dX * ax + dY * ay + dZ * az;
+    double q = fx * fx + fy * fy + fz * fz - ba * ba;
+    q = q > 0.0 ? q : 0.0;
+    dux = -fx; duy = -fy; duz = -fz;
+    if (RR) {
+        const double s = c.rr_kappa * q / ig;     // kappa gamma Q
+        dux -= s * ux; duy -= s * uy; duz -= s * uz;
+    }
+    return q / (ig * ig);
+}
+
+template <class CFG, bool RR>
+__device__ inline bool elec_init(const CFG& c, ElecRR<RR>& e, double t0, double x, double y,
+                                 double z)
+{
+    e.g2q = 0.0;
+    return elec_init(c, static_cast<ElecF64&>(e), t0, x, y, z);
+}
+
+template <int FIELD, class CFG, bool RR>
+__device__ inline void elec_step(const CFG& c, ElecRR<RR>& e)
+{
+    const double h = c.hn;
+    const double ta = e.tau0 + (double)e.n * h;
+    const double hs = (e.n == e.N - 1) ? (e.taue - ta) : h;
+    const double hh = 0.5 * hs;
+    double kX, kY, kZ, kx, ky, kz, aX, aY, aZ, ax, ay, az;
+    const double g2q = rhs_rr_f64<FIELD, RR>(c, ta, e.X, e.Y, e.Z, e.ux, e.uy, e.uz, kX, kY, kZ,
+                                             kx, ky, kz);
+    e.g2q = g2q > e.g2q ? g2q : e.g2q;
+    aX = kX; aY = kY; aZ = kZ; ax = kx; ay = ky; az = kz;
+    rhs_rr_f64<FIELD, RR>(c, ta + hh, e.X + hh * kX, e.Y + hh * kY, e.Z + hh * kZ, e.ux + hh * kx,
+                          e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    aX += 2.0 * kX; aY += 2.0 * kY; aZ += 2.0 * kZ;
+    ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
+    rhs_rr_f64<FIELD, RR>(c, ta + hh, e.X + hh * kX, e.Y + hh * kY, e.Z + hh * kZ, e.ux + hh * kx,
+                          e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    aX += 2.0 * kX; aY += 2.0 * kY; aZ += 2.0 * kZ;
+    ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
+    rhs_rr_f64<FIELD, RR>(c, ta + hs, e.X + hs * kX, e.Y + hs * kY, e.Z + hs * kZ, e.ux + hs * kx,
+                          e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx, ky, kz);
+    const double w6 = hs * (1.0 / 6.0);
+    e.X += w6 * (aX + kX); e.Y += w6 * (aY + kY); e.Z += w6 * (aZ + kZ);
+    e.ux += w6 * (ax + kx); e.uy += w6 * (ay + ky); e.uz += w6 * (az + kz);
+    ++e.n;
+}
+
+// Per-electron extra output: nothing for the plain forms, chi for ElecRR.
+template <class CFG, class E>
+__device__ inline void elec_extra(const CFG&, const E&, double*, int64_t) {}
+
+template <class CFG, bool RR>
+__device__ inline void elec_extra(const CFG& c, const ElecRR<RR>& e, double* chi, int64_t j)
+{
+    if (chi) chi[j] = c.chi_eta * sqrt(e.g2q);
+}
+
+// ---------------------------------------------------------------------------
 // Mixed precision: the field and the RK4 stage arithmetic in float; time,
 // position and the carrier phase in double.  The phase tau - Z is formed in
 // double and reduced to turns in [-1/2, 1/2] before the float sine/cosine
@@ -450,12 +533,14 @@ struct PushIO {
     int32_t spa; int64_t n_slots;
     double* ux; double* uy; double* uz; double* xf; double* yf; double* zf;
     unsigned long long* queue;
+    double* chi = nullptr;     // per-slot largest chi (radiation-reaction push), optional
 };
 
 __device__ inline void write_nan(const PushIO& io, int64_t j)
 {
     const double q = __builtin_nan("");
     io.ux[j] = q; io.uy[j] = q; io.uz[j] = q; io.xf[j] = q; io.yf[j] = q; io.zf[j] = q;
+    if (io.chi) io.chi[j] = q;
 }
 
 // Wave-cooperative refill: lanes with need == true get consecutive queue
@@ -503,6 +588,7 @@ __global__ void __launch_bounds__(256) push_kernel(DevCfg c, PushIO io)
                         if (e.N <= 0) {
                             elec_final(c, e, io.ux[j], io.uy[j], io.uz[j], io.xf[j], io.yf[j],
                                        io.zf[j]);
+                            elec_extra(c, e, io.chi, j);
                             idx = -1;
                         }
                     }
@@ -515,6 +601,7 @@ __global__ void __launch_bounds__(256) push_kernel(DevCfg c, PushIO io)
             if (e.n == e.N) {
                 elec_final(c, e, io.ux[idx], io.uy[idx], io.uz[idx], io.xf[idx], io.yf[idx],
                            io.zf[idx]);
+                elec_extra(c, e, io.chi, idx);
                 idx = -1;
             }
         }

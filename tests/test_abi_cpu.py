@@ -163,3 +163,21 @@ def test_hist2d_spec_layout():
     from paper_2509_01741_amd import binding as B
     assert C.sizeof(B.rpdla_hist2d_spec) == 40
     assert B.rpdla_hist2d_spec.a_lo.offset == 8 and B.rpdla_hist2d_spec.b_hi.offset == 32
+
+
+def test_push_rr_validation():
+    from paper_2509_01741_amd import binding as B
+    lib = B.lib
+    L = B.rpdla_laser_init_intensity(0.8e-6, 2.5e-6, 30e-15, 5e22)
+    p = C.c_void_p(0)
+    args = lambda rr, n, spa: (C.byref(L), rr, n, p, p, p, p, spa, p, p, p, p, p, p, p, p)
+    assert lib.rpdla_push_rr(*args(2, 4, 1)) == B.RPDLA_EINVAL
+    assert lib.rpdla_push_rr(*args(-1, 4, 1)) == B.RPDLA_EINVAL
+    assert lib.rpdla_push_rr(*args(1, -1, 1)) == B.RPDLA_EINVAL
+    assert lib.rpdla_push_rr(*args(1, 4, 0)) == B.RPDLA_EINVAL
+    assert lib.rpdla_push_rr(*args(1, 4, 1)) == B.RPDLA_EINVAL      # null pointers
+    assert lib.rpdla_push_rr(*args(1, 0, 1)) == B.RPDLA_OK
+    bad = B.rpdla_laser_init_intensity(0.8e-6, 2.5e-6, 30e-15, 5e22)
+    bad.tau_fwhm = -1.0
+    assert lib.rpdla_push_rr(C.byref(bad), 1, 0, p, p, p, p, 1, p, p, p, p, p, p, p,
+                             p) == B.RPDLA_EINVAL
