@@ -60,6 +60,7 @@ _lib = None
 _D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _U64 = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 _I32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 
 
 def lib():
@@ -104,6 +105,11 @@ def lib():
                                    _D, _D]),
         "orc_push_rr": (None, [LP, C.c_int, C.c_int64, _D, _D, _D, _D, C.c_int, _D, _D, _D, _D,
                                _D, _D, _D]),
+        "orc_push_one_adaptive": (C.c_int, [LP, C.POINTER(Adaptive), C.c_double, C.c_double,
+                                            _D, _D, _D, _D, _D, _I64, _I64]),
+        "orc_push_adaptive": (None, [LP, C.POINTER(Adaptive), C.c_int64, _D, _D, _D, _D, C.c_int,
+                                     _D, _D, _D, _D, _D, _D, _D, _I64, _I64]),
+        "orc_dp_tableau": (None, [_D, _D, _D, _D]),
         "orc_ne_ip_table": (C.POINTER(C.c_double), []),
     }
     for name, (res, args) in sig.items():
@@ -308,6 +314,46 @@ def push_rr(L: Laser, rr, t_birth, x0, y0, z0, slots_per_atom):
     lib().orc_push_rr(C.byref(L), int(rr), n, t_birth, _d(x0), _d(y0), _d(z0), slots_per_atom,
                       *out)
     return tuple(out)
+
+
+class Adaptive(C.Structure):
+    """Controlled-step push settings (see orc_push_one_adaptive)."""
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h_max", C.c_double),
+                ("k_tol", C.c_double), ("max_steps", C.c_int64)]
+
+
+def adaptive(rtol=1e-9, atol=1e-9, h_max=None, k_tol=1e-10, max_steps=10_000_000, L=None):
+    """Settings; h_max defaults to ten of L's steps dt."""
+    if h_max is None:
+        h_max = 10.0 * L.dt
+    return Adaptive(rtol, atol, h_max, k_tol, max_steps)
+
+
+def dp_tableau():
+    """(c, A, b5, b4) of the oracle's embedded pair."""
+    c, a, b5, b4 = np.zeros(7), np.zeros(49), np.zeros(7), np.zeros(7)
+    lib().orc_dp_tableau(c, a, b5, b4)
+    return c, a.reshape(7, 7), b5, b4
+
+
+def push_one_adaptive(L: Laser, A: Adaptive, t0, t_end, x0, u0):
+    """(xf, uf, t_stop, accepted, rejected, status)."""
+    xf, uf, ts = np.zeros(3), np.zeros(3), np.zeros(1)
+    na, nr = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
+    st = lib().orc_push_one_adaptive(C.byref(L), C.byref(A), t0, t_end, _d(x0), _d(u0), xf, uf,
+                                     ts, na, nr)
+    return xf, uf, float(ts[0]), int(na[0]), int(nr[0]), st
+
+
+def push_adaptive(L: Laser, A: Adaptive, t_birth, x0, y0, z0, slots_per_atom):
+    """(ux, uy, uz, xf, yf, zf, t_stop, accepted, rejected) per slot."""
+    t_birth = _d(t_birth)
+    n = t_birth.size
+    out = [np.zeros(n) for _ in range(7)]
+    na, nr = np.zeros(n, dtype=np.int64), np.zeros(n, dtype=np.int64)
+    lib().orc_push_adaptive(C.byref(L), C.byref(A), n, t_birth, _d(x0), _d(y0), _d(z0),
+                            slots_per_atom, *out, na, nr)
+    return tuple(out) + (na, nr)
 
 
 def num_threads() -> int:

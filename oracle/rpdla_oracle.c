@@ -794,3 +794,155 @@ void orc_push_rr(const orc_laser* L, int rr, int64_t n_slots, const double* t_bi
         xf[s] = XF[0]; yf[s] = XF[1]; zf[s] = XF[2];
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Controlled-step push (Sec. 1 and Sec. 2.1: a fifth-order Runge-Kutta method
+ * with a controlled time step, electrons followed until their kinetic energy
+ * no longer changes).
+ *
+ * Readings (the paper names only "fifth order" and "controlled step"):
+ *   - the pair is Dormand-Prince 5(4): seven stages, the fifth-order result
+ *     carried forward, the last stage reused as the next step's first;
+ *   - error of a step: the largest over the six components of
+ *     |y5 - y4| / (atol + rtol max(|y_n|, |y_n+1|)), positions measured as
+ *     k x and momenta as u = p / m c; the step is accepted when it is <= 1;
+ *   - next step: h * min(5, max(0.2, 0.9 err^(-1/5))) (5 when err = 0), at
+ *     most h_max and never past the window end; first step dt;
+ *   - stop at the window end, or earlier at the first accepted step end at
+ *     which gamma differs by at most k_tol (relative) from its value at the
+ *     previous check; checks are made at the first step ends at least one
+ *     optical period after the previous check (the first one a period after
+ *     birth);
+ *   - more than max_steps attempted steps: the electron is reported as NaN.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double rtol, atol;   /* error tolerances (dimensionless, as above)      */
+    double h_max;        /* largest step [s]                               */
+    double k_tol;        /* relative change of gamma regarded as constant  */
+    int64_t max_steps;   /* attempted steps allowed per electron           */
+} orc_adaptive;
+
+/* Dormand-Prince 5(4) tableau */
+static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
+static const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}};
+/* fifth-order weights (= the last row) and the fourth-order ones */
+static const double DP_B5[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
+                                -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
+static const double DP_B4[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
+                                -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+
+static double orc_gamma6(const double Y[6])
+{
+    return sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
+}
+
+/* returns 0, or 1 when max_steps was exceeded */
+int orc_push_one_adaptive(const orc_laser* L, const orc_adaptive* A, double t0, double t_end,
+                          const double x0[3], const double u0[3], double xf[3], double uf[3],
+                          double* t_stop, int64_t* n_acc, int64_t* n_rej)
+{
+    const double k = 2.0 * ORC_PI / L->lambda;
+    const double T = L->lambda / ORC_C;
+    const double scale[6] = {k, k, k, 1.0, 1.0, 1.0};
+    double Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
+    double K[7][6], Yt[6], Y5[6];
+    double t = t0, h = L->dt;
+    double g_ref = orc_gamma6(Y), t_ref = t0;
+    int64_t acc = 0, rej = 0;
+    int status = 0;
+    orc_rhs(L, t, Y, K[0]);
+    while (t < t_end) {
+        if (acc + rej >= A->max_steps) { status = 1; break; }
+        double hs = h < A->h_max ? h : A->h_max;
+        int last = 0;
+        if (hs >= t_end - t) { hs = t_end - t; last = 1; }
+        for (int s = 1; s < 7; ++s) {
+            for (int i = 0; i < 6; ++i) {
+                double acc_i = 0.0;
+                for (int j = 0; j < s; ++j) acc_i += DP_A[s][j] * K[j][i];
+                Yt[i] = Y[i] + hs * acc_i;
+            }
+            orc_rhs(L, t + DP_C[s] * hs, Yt, K[s]);
+        }
+        /* stage 7 was evaluated at the fifth-order result (row 7 = b5) */
+        for (int i = 0; i < 6; ++i) Y5[i] = Yt[i];
+        double err = 0.0;
+        for (int i = 0; i < 6; ++i) {
+            double e = 0.0;
+            for (int j = 0; j < 7; ++j) e += (DP_B5[j] - DP_B4[j]) * K[j][i];
+            e = fabs(hs * e) * scale[i];
+            const double ya = fabs(Y[i]) * scale[i], yb = fabs(Y5[i]) * scale[i];
+            const double r = e / (A->atol + A->rtol * (ya > yb ? ya : yb));
+            if (r > err) err = r;
+        }
+        if (err <= 1.0) {
+            t = last ? t_end : t + hs;
+            for (int i = 0; i < 6; ++i) { Y[i] = Y5[i]; K[0][i] = K[6][i]; }
+            ++acc;
+            if (last) break;
+            if (t >= t_ref + T) {
+                const double g = orc_gamma6(Y);
+                if (fabs(g - g_ref) <= A->k_tol * g) break;
+                g_ref = g;
+                t_ref = t;
+            }
+        } else {
+            ++rej;
+        }
+        double fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, -0.2);
+        if (fac > 5.0) fac = 5.0;
+        if (fac < 0.2) fac = 0.2;
+        h = hs * fac;
+    }
+    for (int i = 0; i < 3; ++i) { xf[i] = Y[i]; uf[i] = Y[3 + i]; }
+    *t_stop = t;
+    *n_acc = acc;
+    *n_rej = rej;
+    if (status) {
+        for (int i = 0; i < 3; ++i) xf[i] = uf[i] = NAN;
+        *t_stop = NAN;
+    }
+    return status;
+}
+
+void orc_push_adaptive(const orc_laser* L, const orc_adaptive* A, int64_t n_slots,
+                       const double* t_birth, const double* x0, const double* y0,
+                       const double* z0, int slots_per_atom, double* ux, double* uy, double* uz,
+                       double* xf, double* yf, double* zf, double* t_stop, int64_t* n_acc,
+                       int64_t* n_rej)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_slots; ++s) {
+        int64_t a = s / slots_per_atom;
+        double t0 = t_birth[s];
+        double ts, te;
+        orc_window(L, z0[a], &ts, &te);
+        if (!(t0 < INFINITY) || !(t0 >= ts - L->dt)) {
+            ux[s] = uy[s] = uz[s] = xf[s] = yf[s] = zf[s] = t_stop[s] = NAN;
+            n_acc[s] = n_rej[s] = 0;
+            continue;
+        }
+        double X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
+        orc_push_one_adaptive(L, A, t0, te, X0, U0, XF, UF, &t_stop[s], &n_acc[s], &n_rej[s]);
+        ux[s] = UF[0]; uy[s] = UF[1]; uz[s] = UF[2];
+        xf[s] = XF[0]; yf[s] = XF[1]; zf[s] = XF[2];
+    }
+}
+
+/* The tableau above, for the tests (c[7], a[7][7] row-major, b5[7], b4[7]). */
+void orc_dp_tableau(double* c, double* a, double* b5, double* b4)
+{
+    for (int i = 0; i < 7; ++i) {
+        c[i] = DP_C[i];
+        b5[i] = DP_B5[i];
+        b4[i] = DP_B4[i];
+        for (int j = 0; j < 7; ++j) a[i * 7 + j] = (j < 6) ? DP_A[i][j] : 0.0;
+    }
+}
