@@ -813,7 +813,8 @@ void orc_push_rr(const orc_laser* L, int rr, int64_t n_slots, const double* t_bi
  *     previous check; checks are made at the first step ends at least one
  *     optical period after the previous check (the first one a period after
  *     birth);
- *   - more than max_steps attempted steps: the electron is reported as NaN.
+ *   - more than max_steps attempted steps, or a step whose error is not a
+ *     number: the electron is reported as NaN.
  * ------------------------------------------------------------------------- */
 typedef struct {
     double rtol, atol;   /* error tolerances (dimensionless, as above)      */
@@ -880,8 +881,9 @@ int orc_push_one_adaptive(const orc_laser* L, const orc_adaptive* A, double t0, 
             e = fabs(hs * e) * scale[i];
             const double ya = fabs(Y[i]) * scale[i], yb = fabs(Y5[i]) * scale[i];
             const double r = e / (A->atol + A->rtol * (ya > yb ? ya : yb));
-            if (r > err) err = r;
+            if (r > err || r != r) err = r;
         }
+        if (err != err) { status = 1; break; }   /* the step produced no number */
         if (err <= 1.0) {
             t = last ? t_end : t + hs;
             for (int i = 0; i < 6; ++i) { Y[i] = Y5[i]; K[0][i] = K[6][i]; }
