@@ -810,9 +810,10 @@ void orc_push_rr(const orc_laser* L, int rr, int64_t n_slots, const double* t_bi
  *     most h_max and never past the window end; first step dt;
  *   - stop at the window end, or earlier at the first accepted step end at
  *     which gamma differs by at most k_tol (relative) from its value at the
- *     previous check; checks are made at the first step ends at least one
- *     optical period after the previous check (the first one a period after
- *     birth);
+ *     previous check; checks are made at the first step ends at least 0.999
+ *     optical period after the previous check (the first one after birth):
+ *     "one period" with a margin, so that steps commensurate with the period
+ *     (h_max = T/20 by default) do not make each check a rounding tie;
  *   - more than max_steps attempted steps, or a step whose error is not a
  *     number: the electron is reported as NaN.
  * ------------------------------------------------------------------------- */
@@ -889,7 +890,7 @@ int orc_push_one_adaptive(const orc_laser* L, const orc_adaptive* A, double t0, 
             for (int i = 0; i < 6; ++i) { Y[i] = Y5[i]; K[0][i] = K[6][i]; }
             ++acc;
             if (last) break;
-            if (t >= t_ref + T) {
+            if (t - t_ref >= 0.999 * T) {
                 const double g = orc_gamma6(Y);
                 if (fabs(g - g_ref) <= A->k_tol * g) break;
                 g_ref = g;
