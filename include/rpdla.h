@@ -225,6 +225,41 @@ rpdla_status rpdla_push_rr(const rpdla_laser* L, int32_t radiation_reaction, int
                            void* stream);
 
 /* ------------------------------------------------------------------------
+ * Controlled-step push (Sec. 1 and Sec. 2.1: a fifth-order Runge-Kutta method
+ * with a controlled, attosecond-range step, electrons followed until their
+ * kinetic energy is constant).  Same slots, window, birth rules and outputs
+ * as rpdla_push (FP64), integrated with the Dormand-Prince 5(4) pair: the
+ * fifth-order result is carried, the last stage reused as the next first.
+ * A step's error is the largest over (k x, k y, k z, ux, uy, uz) of
+ * |y5 - y4| / (atol + rtol max(|y_n|, |y_n+1|)); accepted when <= 1; the
+ * next step is h min(5, max(0.2, 0.9 err^(-1/5))), at most h_max and never
+ * past the window end; the first step is L->dt.  The electron stops at the
+ * window end, or at the first accepted step end at least 0.999 optical period
+ * after the previous check where gamma changed by at most k_tol (relative;
+ * k_tol < 0: never early).  More than max_steps attempted steps, or a step
+ * whose error estimate is not a number: NaN outputs.
+ * t_stop: device double[n_slots] out [s] or NULL (NaN for unborn, invalid or
+ * failed slots); steps_accepted / steps_rejected: device int64[n_slots] out
+ * or NULL (0 for unborn slots).
+ * EINVAL: bad laser, NULL A, rtol or atol negative or both 0, non-finite
+ * h_max or k_tol, max_steps < 1, n_slots < 0, slots_per_atom < 1, null
+ * pointers (other than the optional outputs) with n_slots > 0.  Uses a small
+ * stream-ordered device allocation for its work queue.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double rtol, atol;    /* error tolerances (dimensionless); e.g. 1e-9, 1e-9   */
+    double h_max;         /* largest step [s]; <= 0: 10 L->dt                    */
+    double k_tol;         /* constant-energy tolerance; e.g. 1e-10; < 0: never   */
+    int64_t max_steps;    /* attempted steps allowed per electron (>= 1)         */
+} rpdla_adaptive;
+
+rpdla_status rpdla_push_adaptive(const rpdla_laser* L, const rpdla_adaptive* A, int64_t n_slots,
+                                 const double* t_birth, const double* x0, const double* y0,
+                                 const double* z0, int32_t slots_per_atom, double* ux, double* uy,
+                                 double* uz, double* xf, double* yf, double* zf, double* t_stop,
+                                 int64_t* steps_accepted, int64_t* steps_rejected, void* stream);
+
+/* ------------------------------------------------------------------------
  * Per-electron outputs (text after Eq. (14); Sec. 2.2, Fig. 5): kinetic
  * energy K = m c^2 u^2 / (gamma + 1) [MeV] (= (gamma - 1) m c^2 without
  * cancellation), polar emission angle theta = atan2(|u_perp|, u_z), azimuth

@@ -54,6 +54,16 @@ class rpdla_hist_spec(C.Structure):
                 ("logE_max_MeV", C.c_double), ("angle", C.c_int32)]
 
 
+class rpdla_adaptive(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h_max", C.c_double),
+                ("k_tol", C.c_double), ("max_steps", C.c_int64)]
+
+
+def adaptive_settings(rtol=1e-9, atol=1e-9, h_max=0.0, k_tol=1e-10, max_steps=10_000_000):
+    """rpdla_adaptive with the library's defaults (h_max <= 0: ten steps dt)."""
+    return rpdla_adaptive(rtol, atol, h_max, k_tol, max_steps)
+
+
 class rpdla_hist2d_spec(C.Structure):
     _fields_ = [("na", C.c_int32), ("nb", C.c_int32), ("a_lo", C.c_double), ("a_hi", C.c_double),
                 ("b_lo", C.c_double), ("b_hi", C.c_double)]
@@ -78,6 +88,8 @@ def _load():
         "rpdla_birth_phase": (i32, [LP, i64, vp, vp, vp, vp, i32, vp, vp, vp]),
         "rpdla_push_rr": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
                                 vp]),
+        "rpdla_push_adaptive": (i32, [LP, C.POINTER(rpdla_adaptive), i64, vp, vp, vp, vp, i32,
+                                      vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_histogram2d": (i32, [i64, vp, vp, vp, C.POINTER(rpdla_hist2d_spec), vp, vp, vp]),
         "rpdla_push": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
@@ -248,6 +260,32 @@ def rpdla_push_rr(L, radiation_reaction, t_birth, x0, y0, z0, slots_per_atom, ou
                              _dev(uz, "uz", n), _dev(xf, "xf", n), _dev(yf, "yf", n),
                              _dev(zf, "zf", n), cp, _stream(stream)), "rpdla_push_rr")
     return tuple(out) + (chi_max,)
+
+
+def rpdla_push_adaptive(L, A, t_birth, x0, y0, z0, slots_per_atom, out=None, want_extra=True,
+                        stream=None):
+    """Controlled-step FP64 push; returns (ux, uy, uz, xf, yf, zf, t_stop,
+    steps_accepted, steps_rejected), the last three None when want_extra is
+    False."""
+    n = t_birth.numel()
+    na = (n + slots_per_atom - 1) // slots_per_atom
+    if out is None:
+        out = tuple(_empty(n, like=t_birth) for _ in range(6))
+    ux, uy, uz, xf, yf, zf = out
+    ts = acc = rej = None
+    if want_extra:
+        ts = _empty(n, like=t_birth)
+        acc = torch.empty(n, dtype=torch.int64, device=t_birth.device)
+        rej = torch.empty(n, dtype=torch.int64, device=t_birth.device)
+    _check(lib.rpdla_push_adaptive(
+        C.byref(L), C.byref(A), n, _dev(t_birth, "t_birth", n), _dev(x0, "x0", na),
+        _dev(y0, "y0", na), _dev(z0, "z0", na), slots_per_atom, _dev(ux, "ux", n),
+        _dev(uy, "uy", n), _dev(uz, "uz", n), _dev(xf, "xf", n), _dev(yf, "yf", n),
+        _dev(zf, "zf", n), _dev(ts, "t_stop", n) if ts is not None else None,
+        _dev(acc, "steps_accepted", n, torch.int64) if acc is not None else None,
+        _dev(rej, "steps_rejected", n, torch.int64) if rej is not None else None,
+        _stream(stream)), "rpdla_push_adaptive")
+    return tuple(out) + (ts, acc, rej)
 
 
 def rpdla_epilogue(ux, uy, uz, out=None, stream=None):

@@ -153,6 +153,8 @@ DevCfg make_cfg(const rpdla_laser* L)
     const double re = kQe * kQe / (4.0 * kPi * kEps0 * kMe * kC * kC);   // classical radius
     c.rr_kappa = 2.0 / 3.0 * k * re;
     c.chi_eta = kHbar * om / (kMe * kC * kC);
+    c.ad_rtol = 1e-9; c.ad_atol = 1e-9; c.ad_hmax = 10.0 * c.hn; c.ad_ktol = 1e-10;
+    c.ad_max_steps = 10000000;
     return c;
 }
 
@@ -244,6 +246,17 @@ rpdla_status launch_push_rr(const DevCfg& c, bool rr, const rpdla::PushIO& io, h
         const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
         hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
     }
+    RPDLA_HIP(hipGetLastError());
+    return RPDLA_OK;
+}
+
+template <int FIELD>
+rpdla_status launch_push_dp(const DevCfg& c, const rpdla::PushIO& io, hipStream_t st)
+{
+    const Shape sh = get_shape(kKindPush, FIELD, RPDLA_FP64);
+    auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecDP>;
+    const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
     RPDLA_HIP(hipGetLastError());
     return RPDLA_OK;
 }
@@ -440,6 +453,53 @@ rpdla_status rpdla_push_rr(const rpdla_laser* L, int32_t radiation_reaction, int
     case 5: st = launch_push_rr<5>(c, rr, io, s); break;
     case 10: st = launch_push_rr<10>(c, rr, io, s); break;
     default: st = launch_push_rr<11>(c, rr, io, s); break;
+    }
+    hipError_t fe = hipFreeAsync(q, s);
+    if (st != RPDLA_OK) return st;
+    if (fe != hipSuccess) return fail(RPDLA_EHIP, "hipFreeAsync: %s", hipGetErrorString(fe));
+    return RPDLA_OK;
+}
+
+rpdla_status rpdla_push_adaptive(const rpdla_laser* L, const rpdla_adaptive* A, int64_t n_slots,
+                                 const double* t_birth, const double* x0, const double* y0,
+                                 const double* z0, int32_t slots_per_atom, double* ux, double* uy,
+                                 double* uz, double* xf, double* yf, double* zf, double* t_stop,
+                                 int64_t* steps_accepted, int64_t* steps_rejected, void* stream)
+{
+    rpdla_status st = check_laser(L);
+    if (st != RPDLA_OK) return st;
+    if (!A) return fail(RPDLA_EINVAL, "adaptive settings are NULL");
+    if (!(is_fin(A->rtol) && is_fin(A->atol) && A->rtol >= 0.0 && A->atol >= 0.0 &&
+          A->rtol + A->atol > 0.0))
+        return fail(RPDLA_EINVAL, "need rtol, atol >= 0, not both 0");
+    if (!(is_fin(A->h_max) && is_fin(A->k_tol))) return fail(RPDLA_EINVAL, "h_max, k_tol not finite");
+    if (A->max_steps < 1) return fail(RPDLA_EINVAL, "max_steps < 1");
+    if (n_slots < 0) return fail(RPDLA_EINVAL, "n_slots < 0");
+    if (slots_per_atom < 1) return fail(RPDLA_EINVAL, "slots_per_atom < 1");
+    if (n_slots == 0) return RPDLA_OK;
+    if (!t_birth || !x0 || !y0 || !z0 || !ux || !uy || !uz || !xf || !yf || !zf)
+        return fail(RPDLA_EINVAL, "null pointer");
+    if (n_slots > ((int64_t)1 << 40)) return fail(RPDLA_ERANGE, "n_slots too large");
+    DevCfg c = make_cfg(L);
+    c.ad_rtol = A->rtol;
+    c.ad_atol = A->atol;
+    c.ad_hmax = A->h_max > 0.0 ? A->h_max * c.omega : 10.0 * c.hn;
+    c.ad_ktol = A->k_tol;
+    c.ad_max_steps = A->max_steps;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* q = nullptr;
+    RPDLA_HIP(hipMallocAsync((void**)&q, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(64), 0, s, q, (int64_t)1);
+    rpdla::PushIO io{t_birth, x0, y0, z0, slots_per_atom, n_slots, ux, uy, uz, xf, yf, zf, q};
+    io.t_stop = t_stop;
+    io.n_acc = (long long*)steps_accepted;
+    io.n_rej = (long long*)steps_rejected;
+    switch (L->field) {
+    case 1: st = launch_push_dp<1>(c, io, s); break;
+    case 3: st = launch_push_dp<3>(c, io, s); break;
+    case 5: st = launch_push_dp<5>(c, io, s); break;
+    case 10: st = launch_push_dp<10>(c, io, s); break;
+    default: st = launch_push_dp<11>(c, io, s); break;
     }
     hipError_t fe = hipFreeAsync(q, s);
     if (st != RPDLA_OK) return st;

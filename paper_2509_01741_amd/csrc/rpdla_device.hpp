@@ -42,6 +42,10 @@ struct DevCfg {
     double gl_x[4], gl_w[4];       // Gauss-Legendre 4-point nodes / weights on [-1, 1]
     double rr_kappa;               // (2/3) k r_e: Landau-Lifshitz gamma^2 term, normalized
     double chi_eta;                // hbar omega / (m c^2): chi = eta gamma sqrt(Q)
+    // controlled-step push: tolerances, largest step (normalized), constant-energy
+    // tolerance and attempted-step budget per electron
+    double ad_rtol, ad_atol, ad_hmax, ad_ktol;
+    int64_t ad_max_steps;
 };
 
 // The subset of DevCfg the push needs (staged in LDS by the batched push).

@@ -374,14 +374,158 @@ __device__ inline void elec_step(const CFG& c, ElecRR<RR>& e)
     ++e.n;
 }
 
-// Per-electron extra output: nothing for the plain forms, chi for ElecRR.
-template <class CFG, class E>
-__device__ inline void elec_extra(const CFG&, const E&, double*, int64_t) {}
 
-template <class CFG, bool RR>
-__device__ inline void elec_extra(const CFG& c, const ElecRR<RR>& e, double* chi, int64_t j)
+// ---------------------------------------------------------------------------
+// Controlled-step push (Sec. 1, Sec. 2.1: fifth-order Runge-Kutta with a
+// controlled step, run until the kinetic energy is constant).  Dormand-Prince
+// 5(4): seven stages, the fifth-order result carried, the last stage reused
+// as the next first one.  One call of elec_step is one attempted step:
+//   error = max_i |y5_i - y4_i| / (atol + rtol max(|y_i|, |y5_i|)) over
+//           (X, Y, Z, u) in normalized units; accept when <= 1;
+//   next step h min(5, max(0.2, 0.9 err^(-1/5))), capped at h_max and at the
+//   window end; first step dt;
+//   stop at the window end or at the first accepted step end, at least 0.999
+//   optical period (2 pi) after the previous check, where gamma changed by at
+//   most k_tol relative (the margin keeps steps commensurate with the period
+//   from making every check a rounding tie); over the step budget, or when a
+//   step's error is not a number, the electron is NaN.
+// ---------------------------------------------------------------------------
+namespace dp {
+constexpr double c2 = 1.0 / 5.0, c3 = 3.0 / 10.0, c4 = 4.0 / 5.0, c5 = 8.0 / 9.0;
+constexpr double a21 = 1.0 / 5.0;
+constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
+constexpr double a41 = 44.0 / 45.0, a42 = -56.0 / 15.0, a43 = 32.0 / 9.0;
+constexpr double a51 = 19372.0 / 6561.0, a52 = -25360.0 / 2187.0, a53 = 64448.0 / 6561.0,
+                 a54 = -212.0 / 729.0;
+constexpr double a61 = 9017.0 / 3168.0, a62 = -355.0 / 33.0, a63 = 46732.0 / 5247.0,
+                 a64 = 49.0 / 176.0, a65 = -5103.0 / 18656.0;
+// fifth-order weights (b2 = 0, b7 = 0) and fifth minus fourth order
+constexpr double b1 = 35.0 / 384.0, b3 = 500.0 / 1113.0, b4 = 125.0 / 192.0,
+                 b5 = -2187.0 / 6784.0, b6 = 11.0 / 84.0;
+constexpr double e1 = b1 - 5179.0 / 57600.0, e3 = b3 - 7571.0 / 16695.0,
+                 e4 = b4 - 393.0 / 640.0, e5 = b5 + 92097.0 / 339200.0,
+                 e6 = b6 - 187.0 / 2100.0, e7 = -1.0 / 40.0;
+}  // namespace dp
+
+struct ElecDP {
+    double y[6];          // X, Y, Z, ux, uy, uz
+    double k1[6];         // derivative at y (valid once `fresh` is false)
+    double tau, h, taue, g_ref, t_ref;
+    int64_t n, N;         // N = 1 while the electron runs, n = 1 when done
+    long long acc, rej;
+    bool fresh, failed;
+};
+
+template <class CFG>
+__device__ inline bool elec_init(const CFG& c, ElecDP& e, double t0, double x, double y, double z)
 {
-    if (chi) chi[j] = c.chi_eta * sqrt(e.g2q);
+    e.y[0] = x * c.k; e.y[1] = y * c.k; e.y[2] = z * c.k;
+    e.y[3] = e.y[4] = e.y[5] = 0.0;
+    e.tau = t0 * c.omega;
+    const double tz = (c.window == 0) ? e.y[2] : 0.0;
+    e.taue = tz + c.ta_n;
+    e.h = c.hn;
+    e.g_ref = 1.0;
+    e.t_ref = e.tau;
+    e.acc = e.rej = 0;
+    e.fresh = true;
+    e.failed = false;
+    e.n = 0;
+    e.N = 0;
+    if (!(e.tau >= tz - c.tb_n - c.hn)) return false;
+    e.N = (e.taue > e.tau) ? 1 : 0;
+    return true;
+}
+
+template <int FIELD, class CFG>
+__device__ inline void dp_rhs(const CFG& c, double tau, const double* y, double* k)
+{
+    rhs_f64<FIELD>(c, tau, y[0], y[1], y[2], y[3], y[4], y[5], k[0], k[1], k[2], k[3], k[4], k[5]);
+}
+
+template <int FIELD, class CFG>
+__device__ inline void elec_step(const CFG& c, ElecDP& e)
+{
+    using namespace dp;
+    if (e.fresh) {
+        dp_rhs<FIELD>(c, e.tau, e.y, e.k1);
+        e.fresh = false;
+    }
+    if (e.acc + e.rej >= c.ad_max_steps) {
+        e.failed = true;
+        e.n = e.N;
+        return;
+    }
+    double hs = e.h < c.ad_hmax ? e.h : c.ad_hmax;
+    bool last = false;
+    if (hs >= e.taue - e.tau) { hs = e.taue - e.tau; last = true; }
+    double k2[6], k3[6], k4[6], k5[6], k6[6], k7[6], yt[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) yt[i] = e.y[i] + hs * (a21 * e.k1[i]);
+    dp_rhs<FIELD>(c, e.tau + c2 * hs, yt, k2);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) yt[i] = e.y[i] + hs * (a31 * e.k1[i] + a32 * k2[i]);
+    dp_rhs<FIELD>(c, e.tau + c3 * hs, yt, k3);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) yt[i] = e.y[i] + hs * (a41 * e.k1[i] + a42 * k2[i] + a43 * k3[i]);
+    dp_rhs<FIELD>(c, e.tau + c4 * hs, yt, k4);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        yt[i] = e.y[i] + hs * (a51 * e.k1[i] + a52 * k2[i] + a53 * k3[i] + a54 * k4[i]);
+    dp_rhs<FIELD>(c, e.tau + c5 * hs, yt, k5);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        yt[i] = e.y[i] + hs * (a61 * e.k1[i] + a62 * k2[i] + a63 * k3[i] + a64 * k4[i] +
+                               a65 * k5[i]);
+    dp_rhs<FIELD>(c, e.tau + hs, yt, k6);
+    double y5[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        y5[i] = e.y[i] + hs * (b1 * e.k1[i] + b3 * k3[i] + b4 * k4[i] + b5 * k5[i] + b6 * k6[i]);
+    dp_rhs<FIELD>(c, e.tau + hs, y5, k7);
+    double err = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const double d = fabs(hs * (e1 * e.k1[i] + e3 * k3[i] + e4 * k4[i] + e5 * k5[i] +
+                                    e6 * k6[i] + e7 * k7[i]));
+        const double ya = fabs(e.y[i]), yb = fabs(y5[i]);
+        const double r = d / (c.ad_atol + c.ad_rtol * (ya > yb ? ya : yb));
+        err = (r > err || r != r) ? r : err;
+    }
+    if (err != err) {            // the step produced no number: give up on this electron
+        e.failed = true;
+        e.n = e.N;
+        return;
+    }
+    if (err <= 1.0) {
+        e.tau = last ? e.taue : e.tau + hs;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) { e.y[i] = y5[i]; e.k1[i] = k7[i]; }
+        ++e.acc;
+        if (last) { e.n = e.N; return; }
+        if (e.tau - e.t_ref >= 0.999 * (2.0 * 3.14159265358979323846)) {
+            const double g = sqrt(1.0 + e.y[3] * e.y[3] + e.y[4] * e.y[4] + e.y[5] * e.y[5]);
+            if (fabs(g - e.g_ref) <= c.ad_ktol * g) { e.n = e.N; return; }
+            e.g_ref = g;
+            e.t_ref = e.tau;
+        }
+    } else {
+        ++e.rej;
+    }
+    double fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, -0.2);
+    fac = fac > 5.0 ? 5.0 : (fac < 0.2 ? 0.2 : fac);
+    e.h = hs * fac;
+}
+
+template <class CFG>
+__device__ inline void elec_final(const CFG& c, const ElecDP& e, double& ux, double& uy,
+                                  double& uz, double& xf, double& yf, double& zf)
+{
+    const double q = __builtin_nan("");
+    ux = e.failed ? q : e.y[3]; uy = e.failed ? q : e.y[4]; uz = e.failed ? q : e.y[5];
+    xf = e.failed ? q : e.y[0] * c.inv_k;
+    yf = e.failed ? q : e.y[1] * c.inv_k;
+    zf = e.failed ? q : e.y[2] * c.inv_k;
 }
 
 // ---------------------------------------------------------------------------
@@ -533,14 +677,47 @@ struct PushIO {
     int32_t spa; int64_t n_slots;
     double* ux; double* uy; double* uz; double* xf; double* yf; double* zf;
     unsigned long long* queue;
-    double* chi = nullptr;     // per-slot largest chi (radiation-reaction push), optional
+    double* chi = nullptr;           // largest chi (radiation-reaction push), optional
+    double* t_stop = nullptr;        // stop time [s] (controlled-step push), optional
+    long long* n_acc = nullptr;      // accepted / rejected steps (controlled-step push)
+    long long* n_rej = nullptr;
 };
 
+// Electron forms with outputs beyond momentum and position.
+template <class E> struct HasExtra { static constexpr bool value = false; };
+template <bool RR> struct HasExtra<ElecRR<RR>> { static constexpr bool value = true; };
+template <> struct HasExtra<ElecDP> { static constexpr bool value = true; };
+
+template <bool EXTRA>
 __device__ inline void write_nan(const PushIO& io, int64_t j)
 {
     const double q = __builtin_nan("");
     io.ux[j] = q; io.uy[j] = q; io.uz[j] = q; io.xf[j] = q; io.yf[j] = q; io.zf[j] = q;
-    if (io.chi) io.chi[j] = q;
+    if (EXTRA) {
+        if (io.chi) io.chi[j] = q;
+        if (io.t_stop) io.t_stop[j] = q;
+        if (io.n_acc) io.n_acc[j] = 0;
+        if (io.n_rej) io.n_rej[j] = 0;
+    }
+}
+
+// Per-electron extra outputs: nothing for the plain forms, chi for ElecRR,
+// stop time and step counts for ElecDP.
+template <class CFG, class E>
+__device__ inline void elec_extra(const CFG&, const E&, const PushIO&, int64_t) {}
+
+template <class CFG, bool RR>
+__device__ inline void elec_extra(const CFG& c, const ElecRR<RR>& e, const PushIO& io, int64_t j)
+{
+    if (io.chi) io.chi[j] = c.chi_eta * sqrt(e.g2q);
+}
+
+template <class CFG>
+__device__ inline void elec_extra(const CFG& c, const ElecDP& e, const PushIO& io, int64_t j)
+{
+    if (io.t_stop) io.t_stop[j] = e.failed ? __builtin_nan("") : e.tau * c.inv_omega;
+    if (io.n_acc) io.n_acc[j] = e.acc;
+    if (io.n_rej) io.n_rej[j] = e.rej;
 }
 
 // Wave-cooperative refill: lanes with need == true get consecutive queue
@@ -577,18 +754,18 @@ __global__ void __launch_bounds__(256) push_kernel(DevCfg c, PushIO io)
                 } else {
                     const double t0 = io.tb[j];
                     if (!(t0 < __builtin_inf())) {
-                        write_nan(io, j);
+                        write_nan<HasExtra<ELEC>::value>(io, j);
                     } else {
                         const int64_t a = j / io.spa;
                         if (!elec_init(c, e, t0, io.x0[a], io.y0[a], io.z0[a])) {
-                            write_nan(io, j);
+                            write_nan<HasExtra<ELEC>::value>(io, j);
                             continue;
                         }
                         idx = j;
                         if (e.N <= 0) {
                             elec_final(c, e, io.ux[j], io.uy[j], io.uz[j], io.xf[j], io.yf[j],
                                        io.zf[j]);
-                            elec_extra(c, e, io.chi, j);
+                            elec_extra(c, e, io, j);
                             idx = -1;
                         }
                     }
@@ -601,7 +778,7 @@ __global__ void __launch_bounds__(256) push_kernel(DevCfg c, PushIO io)
             if (e.n == e.N) {
                 elec_final(c, e, io.ux[idx], io.uy[idx], io.uz[idx], io.xf[idx], io.yf[idx],
                            io.zf[idx]);
-                elec_extra(c, e, io.chi, idx);
+                elec_extra(c, e, io, idx);
                 idx = -1;
             }
         }

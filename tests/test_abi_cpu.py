@@ -181,3 +181,25 @@ def test_push_rr_validation():
     bad.tau_fwhm = -1.0
     assert lib.rpdla_push_rr(C.byref(bad), 1, 0, p, p, p, p, 1, p, p, p, p, p, p, p,
                              p) == B.RPDLA_EINVAL
+
+
+def test_push_adaptive_validation():
+    from paper_2509_01741_amd import binding as B
+    lib = B.lib
+    L = B.rpdla_laser_init_intensity(0.8e-6, 3e-6, 30e-15, 1e21)
+    p = C.c_void_p(0)
+
+    def call(A, n=4, spa=1):
+        return lib.rpdla_push_adaptive(C.byref(L), C.byref(A) if A is not None else None, n, p, p,
+                                       p, p, spa, p, p, p, p, p, p, p, p, p, p)
+    ok = B.adaptive_settings()
+    assert call(None) == B.RPDLA_EINVAL
+    assert call(B.adaptive_settings(rtol=-1.0)) == B.RPDLA_EINVAL
+    assert call(B.adaptive_settings(rtol=0.0, atol=0.0)) == B.RPDLA_EINVAL
+    assert call(B.adaptive_settings(h_max=float("inf"))) == B.RPDLA_EINVAL
+    assert call(B.adaptive_settings(max_steps=0)) == B.RPDLA_EINVAL
+    assert call(ok, n=-1) == B.RPDLA_EINVAL
+    assert call(ok, spa=0) == B.RPDLA_EINVAL
+    assert call(ok) == B.RPDLA_EINVAL                # null pointers
+    assert call(ok, n=0) == B.RPDLA_OK
+    assert C.sizeof(B.rpdla_adaptive) == 40
