@@ -134,8 +134,8 @@ def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk):
 
 PUSH_KERNEL_NAME = "push_kernel<5, rpdla::ElecF64>"
 TRAFFIC_CMD = ("rocprofv3 --pmc {ctr} --output-format csv -d $R/gpurun_out/{d} -o run -- python3 "
-               "$R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-mixed --no-batched "
-               "--copy-ref-mib 512")
+               "$R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-mixed --no-adaptive "
+               "--no-batched --copy-ref-mib 512")
 
 
 def _counter_rows(d, counter):
@@ -236,6 +236,7 @@ def main():
     ap.add_argument("--atoms", type=int, default=None, help="override (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size "
@@ -345,6 +346,39 @@ def main():
         )
         log(f"mixed: {mixed}")
 
+    adaptive = None
+    if not args.no_adaptive:
+        # controlled-step push of the same slots (default tolerances, early stop
+        # when the energy is constant): time, steps taken, energies against the
+        # fixed-step FP64 push
+        A = B.adaptive_settings()
+        outs = tuple(torch.empty_like(o) for o in ens.out)
+        a, b = ev(), ev()
+        a.record()
+        r = B.rpdla_push_adaptive(ens.L, A, ens.tb, ens.x, ens.y, ens.z, ens.K, outs)
+        b.record()
+        torch.cuda.synchronize()
+        ad_ms = a.elapsed_time(b)
+        fin = torch.isfinite(ens.tb)
+        u2a = outs[0][fin] ** 2 + outs[1][fin] ** 2 + outs[2][fin] ** 2
+        u2f = ens.out[0][fin] ** 2 + ens.out[1][fin] ** 2 + ens.out[2][fin] ** 2
+        Ka = u2a / (torch.sqrt(1 + u2a) + 1)
+        Kf = u2f / (torch.sqrt(1 + u2f) + 1)
+        rel = (Ka - Kf).abs() / Kf
+        acc = r[7][fin].double()
+        rej = r[8][fin].double()
+        adaptive = dict(
+            push_ms=round(ad_ms, 2),
+            electrons_per_s=int(fin.sum().item()) / (ad_ms * 1e-3),
+            speedup_vs_fixed_step=push_avg / ad_ms,
+            mean_accepted_steps=float(acc.mean().item()),
+            mean_rejected_steps=float(rej.mean().item()),
+            field_evaluations_vs_fixed_step=float(6 * (acc + rej).sum().item() / (4 * steps)),
+            median_rel_energy_diff_vs_fixed_step=float(rel.median().item()),
+            settings=dict(rtol=A.rtol, atol=A.atol, h_max="10 dt", k_tol=A.k_tol),
+        )
+        log(f"adaptive: {adaptive}")
+
     batched = None
     if not args.no_batched:
         batched = {}
@@ -397,6 +431,7 @@ def main():
         "ionize_ms": round(ion_avg, 2),
         "tallies": dict(zip(["fwd", "bwd", "below", "above", "unborn", "nan"], tal)),
         "mixed": mixed,
+        "adaptive": adaptive,
         "batched": batched,
         "cpu_baseline": base,
     }
