@@ -34,6 +34,11 @@ constexpr double kTauA = 2.4188843265857e-17;  // atomic unit of time [s]
 constexpr double kEhEv = 27.211386245988;      // Hartree [eV]
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHbar = 1.054571817e-34;        // reduced Planck constant [J s]
+// Ionization panels are skipped where a rigorous bound keeps ln w (per unit
+// normalized time) below this level: over a window of at most 1e5 normalized
+// time units the skipped part of any survival integral is below 1e5 e^-80
+// = 2e-30, far under the rounding of the integrals (targets -ln u >= 1e-16).
+constexpr double kLnwSkip = -80.0;
 
 // Neon ionization potentials Ne^(k-1)+ -> Ne^k+ [eV] (NIST ASD).
 constexpr double kNeIpEv[10] = {21.564540, 40.96297, 63.4233, 97.1900, 126.247,
@@ -143,7 +148,7 @@ DevCfg make_cfg(const rpdla_laser* L)
         c.adk_c0[s] = lnC2 + log(Ip / kTauA) + (2.0 * ns - 1.0) * (log(2.0 * F0) - log(fconv)) - log(om);
         c.adk_c1h[s] = 0.5 * (2.0 * ns - 1.0);
         c.adk_c2[s] = 2.0 * F0 / (3.0 * fconv);
-        c.adk_a2thr[s] = adk_threshold_a2(c.adk_c0[s], c.adk_c1h[s], c.adk_c2[s], c.lnw_zero - 5.0);
+        c.adk_a2thr[s] = adk_threshold_a2(c.adk_c0[s], c.adk_c1h[s], c.adk_c2[s], kLnwSkip);
     }
     const double ga = sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(6.0 / 5.0));
     const double gb = sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(6.0 / 5.0));
