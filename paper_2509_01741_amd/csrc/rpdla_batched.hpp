@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(256) batch_sample_kernel(BatchArgs A)
 }
 
 template <int FIELD>
-__global__ void __launch_bounds__(256) batch_ionize_kernel(BatchArgs A)
+__global__ void __launch_bounds__(256, 2) batch_ionize_kernel(BatchArgs A)
 {
     extern __shared__ double lds_raw[];
     DevCfg* s_cfg = reinterpret_cast<DevCfg*>(lds_raw);
@@ -130,7 +130,7 @@ __device__ inline T uniform_copy(const T* p)
 // momenta go to the chunk's u arrays (NaN for invalid births; unborn and
 // inactive slots are not written).
 template <int FIELD, class ELEC>
-__global__ void __launch_bounds__(256, 4) batch_push_kernel(BatchArgs A)
+__global__ void __launch_bounds__(256, ElecWaves<ELEC>::value) batch_push_kernel(BatchArgs A)
 {
     extern __shared__ double lds_raw[];
     const int ncfg = A.n_cfg;

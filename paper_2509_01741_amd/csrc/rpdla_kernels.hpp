@@ -735,8 +735,16 @@ __device__ inline int64_t queue_take(unsigned long long* queue, bool need)
     return need ? (int64_t)(base + (unsigned long long)rank) : -1;
 }
 
+// Waves per SIMD each electron form is compiled for (its register budget):
+// FP64 RK4 4 (5 needs a few spills and measured no faster), mixed 6 (lands
+// at 7 without spills, 1-5% faster than 5), controlled-step unbounded (six
+// stored stages, 2 waves).
+template <class E> struct ElecWaves { static constexpr int value = 4; };
+template <> struct ElecWaves<ElecMixed> { static constexpr int value = 6; };
+template <> struct ElecWaves<ElecDP> { static constexpr int value = 1; };
+
 template <int FIELD, class ELEC>
-__global__ void __launch_bounds__(256) push_kernel(DevCfg c, PushIO io)
+__global__ void __launch_bounds__(256, ElecWaves<ELEC>::value) push_kernel(DevCfg c, PushIO io)
 {
     int64_t idx = -1;
     bool exhausted = false;
