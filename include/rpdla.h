@@ -309,10 +309,16 @@ rpdla_status rpdla_histogram2d(int64_t n, const double* a, const double* b, cons
  * |z| < z_r, RNG key (seed, cfg_base + c) for configuration c, charge states
  * k_first..k_last.  Atoms are processed in chunks of atoms_per_chunk per
  * configuration; each chunk runs sample -> ionize -> push -> histogram, the
- * push as ONE persistent launch over every configuration's electrons (one
- * global work queue, lanes refilled as their electron finishes; the
- * configuration table staged in LDS).
- * The chunk's launch sequence is captured once in a hipGraph and replayed.
+ * push as ONE persistent launch over every configuration's electrons: every
+ * configuration has its own work counter, each wave serves one configuration
+ * at a time (its constants copied from an LDS table into scalar registers)
+ * and moves to another with work left when its own runs dry; lanes are
+ * refilled as their electron finishes.
+ * On a non-null stream that is not being captured, with more than one chunk,
+ * the chunk's launch sequence is captured once in a hipGraph (the chunk index
+ * advances in device memory) and replayed per chunk; graphs are cached per
+ * argument set for the process lifetime (up to 32; further argument sets are
+ * enqueued directly).  Otherwise the launches are enqueued directly.
  * counts: device uint64[n_cfg][2][nE][nA], tallies: device uint64[n_cfg][6],
  * accumulated; electron_steps: device uint64[n_cfg] (accumulated) receiving
  * the number of RK4 steps taken per configuration, or NULL.  The chunk's

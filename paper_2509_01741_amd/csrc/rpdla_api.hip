@@ -588,6 +588,10 @@ WsLayout ws_layout(int n_cfg, int64_t apc, int K)
 
 std::mutex g_graph_mu;
 std::vector<std::pair<std::string, hipGraphExec_t>> g_graphs;  // small cache, process lifetime
+// Graphs are never destroyed while the process runs (a replay may still be in
+// flight on its stream); once this many argument sets have been captured,
+// further ones are enqueued directly, without a graph.
+constexpr size_t kMaxGraphs = 32;
 
 template <int FIELD, class ELEC>
 rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipStream_t s)
@@ -632,10 +636,19 @@ rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipSt
     key.append(reinterpret_cast<const char*>(&grid_p), sizeof grid_p);
     key.append(reinterpret_cast<const char*>(&sh), sizeof sh);
     hipGraphExec_t exec = nullptr;
+    bool full = false;
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
         for (auto& kv : g_graphs)
             if (kv.first == key) { exec = kv.second; break; }
+        full = g_graphs.size() >= kMaxGraphs;
+    }
+    if (!exec && full) {
+        for (int64_t i = 0; i < n_chunks; ++i) {
+            rpdla_status r = enqueue_chunk(s);
+            if (r != RPDLA_OK) return r;
+        }
+        return RPDLA_OK;
     }
     if (!exec) {
         hipGraph_t graph = nullptr;

@@ -1,10 +1,10 @@
 // rpdla_batched.hpp -- parameter sweeps in one pass per atom chunk: sampling
 // and ionization over every configuration's atoms, then ONE persistent push
-// launch over every configuration's electrons with a single global work
-// queue (lanes refilled as their electron finishes, so uneven step counts
-// across wavelengths and powers balance themselves) and the configuration
-// table staged in LDS, then one binning pass over the chunk's final momenta
-// into per-configuration energy-angle histograms.
+// launch over every configuration's electrons (per-configuration work
+// counters, each wave serving one configuration at a time from an LDS table,
+// lanes refilled as their electron finishes, so uneven step counts across
+// wavelengths and powers balance themselves), then one binning pass over the
+// chunk's final momenta into per-configuration energy-angle histograms.
 #pragma once
 
 #include "rpdla_kernels.hpp"

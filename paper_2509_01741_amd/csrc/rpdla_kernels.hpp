@@ -213,7 +213,7 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
 }
 
 template <int FIELD>
-__global__ void __launch_bounds__(256) ionize_kernel(
+__global__ void __launch_bounds__(256, 3) ionize_kernel(
     DevCfg c, uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n,
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     int k_first, int k_last, double* __restrict__ t_birth)

@@ -1,5 +1,6 @@
 """Batched persistent sweep (one push launch over several configurations,
-LDS configuration table, fused binning, hipGraph chunk replay) against the
+LDS configuration table, per-configuration queues, separate binning pass,
+hipGraph chunk replay) against the
 single-configuration path and the oracle."""
 import numpy as np
 import pytest
