@@ -154,10 +154,12 @@ def _counter_rows(d, counter):
     return rows
 
 
-def write_traffic_summary(fetch_dir, write_dir, atoms=1_000_000, copy_mib=512, slots_per_atom=10):
+def write_traffic_summary(fetch_dir, write_dir, atoms=1_000_000, copy_mib=512, slots_per_atom=10,
+                          out_json=PROFILE_TRAFFIC_FILE):
     """Turn the FETCH_SIZE and WRITE_SIZE runs (TRAFFIC_CMD) into the push
     kernel's HBM bytes per launch, scaled by what the same counters read for
-    the plain copy of copy_mib MiB, and write profiles/*_traffic.{json,md}."""
+    the plain copy of copy_mib MiB, and write out_json and the .md beside it
+    (profiles/*_traffic.{json,md} by default)."""
     out = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, counter)
@@ -179,7 +181,7 @@ def write_traffic_summary(fetch_dir, write_dir, atoms=1_000_000, copy_mib=512, s
                fetch_scale=f_scale, write_scale=w_scale, kernel_source_hash=kernel_source_hash(),
                command=TRAFFIC_CMD.format(ctr="FETCH_SIZE (then WRITE_SIZE)", d="pmcF|pmcW"),
                summary_command=f"python3 bench.py --traffic-from {fetch_dir} {write_dir}")
-    with open(PROFILE_TRAFFIC_FILE, "w") as fh:
+    with open(out_json, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     md = [
@@ -220,9 +222,10 @@ def write_traffic_summary(fetch_dir, write_dir, atoms=1_000_000, copy_mib=512, s
         f"Kernel source hash {kernel_source_hash()} (bench.py reports this traffic only for",
         "that build of the push kernel).",
     ]
-    with open(PROFILE_TRAFFIC_FILE.replace(".json", ".md"), "w") as fh:
+    with open(out_json.replace(".json", ".md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     print(json.dumps(rec))
+    return rec
 
 
 def main():

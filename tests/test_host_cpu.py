@@ -1,0 +1,75 @@
+"""Host-side pieces that need no GPU: the binding refuses to load without the
+built library (no CPU fallback), bench.py's contract for several GPUs and its
+counter-summary arithmetic, and the experiment driver's reductions."""
+import json
+import math
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    pkg = tmp_path / "pkgcopy"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text("")
+    shutil.copy(os.path.join(ROOT, "paper_2509_01741_amd", "binding.py"), pkg / "binding.py")
+    r = subprocess.run([sys.executable, "-c", "import pkgcopy.binding"], cwd=tmp_path,
+                       capture_output=True, text=True)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "not built" in r.stderr
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def _write_counters(d, counter, rows):
+    d.mkdir(parents=True)
+    with open(d / "run_counter_collection.csv", "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i, (k, v) in enumerate(rows):
+            f.write(f'{i},"{k}",{counter},{v}\n')
+
+
+def test_traffic_summary_arithmetic(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    push = "void rpdla::push_kernel<5, rpdla::ElecF64>(rpdla::DevCfg, rpdla::PushIO)"
+    copy = "__amd_rocclr_copyBuffer"
+    _write_counters(tmp_path / "F", "FETCH_SIZE", [(copy, 262144.0), (push, 1000.0),
+                                                   ("void rpdla::ionize_kernel<5>(x)", 7.0)])
+    _write_counters(tmp_path / "W", "WRITE_SIZE", [(copy, 524288.0), (push, 3000.0),
+                                                   ("void rpdla::ionize_kernel<5>(x)", 9.0)])
+    out = tmp_path / "t.json"
+    rec = bench.write_traffic_summary(str(tmp_path / "F"), str(tmp_path / "W"), out_json=str(out))
+    assert rec["fetch_scale"] == 0.5 and rec["write_scale"] == 1.0
+    assert rec["read_bytes"] == 1000.0 * 1024 / 0.5 and rec["write_bytes"] == 3000.0 * 1024
+    assert rec["algorithmic_bytes"] == 1e6 * 10 * 56 + 1e6 * 24
+    assert json.load(open(out))["bytes_per_launch"] == rec["read_bytes"] + rec["write_bytes"]
+    assert "ionize_kernel<5>" in open(str(out).replace(".json", ".md")).read()
+
+
+def test_experiment_reductions():
+    torch = pytest.importorskip("torch")
+    sys.path.insert(0, ROOT)
+    # loads the built library (no GPU call is made): the reductions are plain
+    # torch on CPU counts
+    from paper_2509_01741_amd import experiments as ex
+    assert abs(ex.f_number_waist(0.8e-6) / 2.546479089470325e-06 - 1) < 1e-15
+    # phase x radius counts: 8 phase bins x 4 radius bins, direction 1 only
+    pr = torch.zeros((2, 8, 4), dtype=torch.int64)
+    pr[1, 0, 0] = 30          # phase bin [0, pi/4): within pi/4 of 0
+    pr[1, 7, 1] = 10          # [7pi/4, 2pi): within pi/4 of 2 pi
+    pr[1, 4, 3] = 60          # around pi
+    assert abs(ex.phase_near_zero_fraction(pr, 1, math.pi / 4) - 0.4) < 1e-12
+    assert math.isnan(ex.phase_near_zero_fraction(pr, 0, math.pi / 4))
+    assert ex.radius_quantile(pr, 1, 4e-6, 0.9) == 4e-6   # 60% in the last radius bin
+    assert ex.radius_quantile(pr, 1, 4e-6, 0.3) == 1e-6
