@@ -332,6 +332,18 @@ rpdla_status rpdla_histogram2d(int64_t n, const double* a, const double* b, cons
  * ------------------------------------------------------------------------ */
 size_t rpdla_batched_workspace_bytes(int32_t n_cfg, int64_t atoms_per_chunk, int32_t k_first,
                                      int32_t k_last);
+
+/* Where the last chunk's particle data sits in the workspace once
+ * rpdla_run_batched has completed on its stream: byte offsets[7] of
+ * x, y, z (double[n_cfg][atoms_per_chunk], m), t_birth, ux, uy, uz
+ * (double[n_cfg][atoms_per_chunk][K], K = k_last - k_first + 1), atom a of
+ * configuration c being atom chunk_start + a of that configuration.  Entries
+ * past atoms_per_cfg in a partial last chunk, and the momenta of unborn
+ * slots, are not written (stale).  The layout depends only on the sizes.
+ * EINVAL: NULL offsets, invalid sizes. */
+#define RPDLA_WS_NARRAYS 7
+rpdla_status rpdla_batched_workspace_layout(int32_t n_cfg, int64_t atoms_per_chunk,
+                                           int32_t k_first, int32_t k_last, size_t* offsets);
 rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t seed,
                                uint32_t cfg_base, int64_t atoms_per_cfg, int64_t atoms_per_chunk,
                                double r_factor, int32_t k_first, int32_t k_last,

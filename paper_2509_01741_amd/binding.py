@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -90,6 +91,7 @@ def _load():
                                 vp]),
         "rpdla_push_adaptive": (i32, [LP, C.POINTER(rpdla_adaptive), i64, vp, vp, vp, vp, i32,
                                       vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "rpdla_batched_workspace_layout": (i32, [i32, i64, i32, i32, C.POINTER(C.c_size_t)]),
         "rpdla_histogram2d": (i32, [i64, vp, vp, vp, C.POINTER(rpdla_hist2d_spec), vp, vp, vp]),
         "rpdla_push": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
@@ -345,6 +347,31 @@ def rpdla_get_launch_shape(kernel, field, precision):
 
 def rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last) -> int:
     return int(lib.rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last))
+
+
+RPDLA_WS_NARRAYS = 7
+WS_ARRAYS = ("x", "y", "z", "t_birth", "ux", "uy", "uz")
+
+
+def rpdla_batched_workspace_layout(n_cfg, atoms_per_chunk, k_first, k_last) -> dict:
+    """Byte offsets of the last chunk's arrays in the batched workspace."""
+    off = (C.c_size_t * RPDLA_WS_NARRAYS)()
+    _check(lib.rpdla_batched_workspace_layout(n_cfg, atoms_per_chunk, k_first, k_last, off),
+           "rpdla_batched_workspace_layout")
+    return dict(zip(WS_ARRAYS, (int(v) for v in off)))
+
+
+def batched_chunk_arrays(workspace, n_cfg, atoms_per_chunk, k_first, k_last) -> dict:
+    """Views (float64 tensors) of the last chunk's arrays inside a workspace:
+    x, y, z [n_cfg, apc] and t_birth, ux, uy, uz [n_cfg, apc, K]."""
+    lay = rpdla_batched_workspace_layout(n_cfg, atoms_per_chunk, k_first, k_last)
+    K = k_last - k_first + 1
+    out = {}
+    for name, o in lay.items():
+        shape = (n_cfg, atoms_per_chunk) if name in ("x", "y", "z") else (n_cfg, atoms_per_chunk, K)
+        cnt = int(np.prod(shape))
+        out[name] = workspace[o:o + 8 * cnt].view(torch.float64).view(*shape)
+    return out
 
 
 def rpdla_run_batched(lasers, seed, cfg_base, atoms_per_cfg, atoms_per_chunk, r_factor, k_first,

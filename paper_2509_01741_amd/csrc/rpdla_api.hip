@@ -678,6 +678,18 @@ size_t rpdla_batched_workspace_bytes(int32_t n_cfg, int64_t atoms_per_chunk, int
     return ws_layout(n_cfg, atoms_per_chunk, k_last - k_first + 1).total;
 }
 
+rpdla_status rpdla_batched_workspace_layout(int32_t n_cfg, int64_t atoms_per_chunk,
+                                           int32_t k_first, int32_t k_last, size_t* offsets)
+{
+    if (!offsets) return fail(RPDLA_EINVAL, "offsets is NULL");
+    if (n_cfg < 1 || atoms_per_chunk < 1 || k_first < 1 || k_last < k_first || k_last > 10)
+        return fail(RPDLA_EINVAL, "invalid sizes");
+    const WsLayout w = ws_layout(n_cfg, atoms_per_chunk, k_last - k_first + 1);
+    const size_t o[RPDLA_WS_NARRAYS] = {w.x, w.y, w.z, w.tb, w.ux, w.uy, w.uz};
+    for (int i = 0; i < RPDLA_WS_NARRAYS; ++i) offsets[i] = o[i];
+    return RPDLA_OK;
+}
+
 rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t seed,
                                uint32_t cfg_base, int64_t atoms_per_cfg, int64_t atoms_per_chunk,
                                double r_factor, int32_t k_first, int32_t k_last, int32_t precision,
