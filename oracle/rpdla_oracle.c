@@ -23,6 +23,9 @@
  *   - Newton-Lorentz equations .................. Eqs. (7)-(14)
  *   - kinetic energy and azimuth ................ text after Eq. (14); Sec. 2.2, Fig. 5 text
  *   - forward / backward classification ......... Sec. 2.2 (Figs. 4, 7-9, 13-16)
+ *   - birth phase, hollow-cylinder ions, 2-D maps  Sec. 2.2, Figs. 6, 8, 13, 14
+ *   - radiation reaction and quantum parameter .. Sec. 2.1, Eqs. (3)-(6)
+ *   - controlled-step fifth-order push .......... Sec. 1 and Sec. 2.1
  *
  * Readings where the paper is silent or garbled are listed next to the code
  * that takes them.  Parity status of every function: pinned by the CPU tests
