@@ -31,6 +31,16 @@ C_LIGHT = 299792458.0
 # polynomial implementations): 4 x (223 field + 27 Lorentz) + 85 RK4 = 1085.
 ALGO_FLOP_PER_STEP = 1085.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# FP32 vector peak as published (it counts packed two-wide FP32 operations;
+# this build compiles without packed FP32, so one-wide FP32 peaks at 78.6)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+PROFILE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "push_rp_ne_fp64_100k_counters.json")
+COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32",
+            "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
+            "SQ_INSTS_VALU_TRANS_F32"]
+COUNTERS_CMD = ("rocprofv3 --pmc " + " ".join(COUNTERS) + " --output-format csv -d "
+                "$R/gpurun_out/pmcS -o run -- python3 $R/bench.py --steps 1 --warmup 0 --atoms 100000 "
+                "--no-cpu-baseline --no-adaptive --no-batched")
 PROFILE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_fp64_rp_ne_fp64_1m_traffic.json")
 # sources that define the FP64 push kernel (its traffic figure is tied to them)
 KERNEL_SOURCES = ["rpdla_device.hpp", "rpdla_kernels.hpp", "rpdla_fastmath.hpp",
@@ -228,9 +238,81 @@ def write_traffic_summary(fetch_dir, write_dir, atoms=1_000_000, copy_mib=512, s
     return rec
 
 
+def write_counter_summary(counter_dir, bench_json, out_json=PROFILE_COUNTERS_FILE):
+    """Turn the counter run (COUNTERS_CMD) and that run's bench line into
+    per-electron-step FLOPs and issue rates of the FP64 and mixed pushes, and
+    write out_json and the .md beside it."""
+    import csv
+    import glob
+    vals = {}
+    for f in glob.glob(os.path.join(counter_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                for form, name in (("fp64", "push_kernel<5, rpdla::ElecF64>"),
+                                   ("mixed", "push_kernel<5, rpdla::ElecMixed>")):
+                    if name in r["Kernel_Name"] and "batch" not in r["Kernel_Name"]:
+                        d = vals.setdefault(form, {})
+                        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    line = [l for l in open(bench_json) if l.startswith("{")][-1]
+    b = json.loads(line)
+    steps = b["config"]["electron_steps"]
+    ms = {"fp64": b["roofline"]["push_ms"], "mixed": b["mixed"]["push_ms"]}
+    rec = dict(workload="rp_ne_fp64_1m at 1e5 atoms", electron_steps=steps,
+               kernel_source_hash=kernel_source_hash(), command=COUNTERS_CMD,
+               summary_command=f"python3 bench.py --counters-from {counter_dir} BENCH_STDOUT")
+    md = ["# FP64 and mixed push counters, 1e5 atoms of the benchmark ensemble (states 1-10, order 5)",
+          "", "One counter run, then the summary (from the repository root, R=$GRAFT_REPO_ROOT):", "",
+          "```", "cd /tmp && export TMPDIR=/tmp", COUNTERS_CMD + " > $R/gpurun_out/pmcS.json",
+          "cd $R && python3 bench.py --counters-from gpurun_out/pmcS gpurun_out/pmcS.json", "```",
+          "", f"{steps:.4e} electron-steps per push launch.", "",
+          "| counter (summed over the dispatch) | FP64 push | mixed push |", "|---|---|---|"]
+    for ctr in COUNTERS:
+        md.append(f"| {ctr} | {vals['fp64'].get(ctr, float('nan')):.4e} | "
+                  f"{vals['mixed'].get(ctr, float('nan')):.4e} |")
+    md += ["", "Derived (SQ counts are per wave instruction; a wave is 64 lanes):", ""]
+    for form in ("fp64", "mixed"):
+        v = vals[form]
+        f64 = 64 * v.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0)
+        f32 = 64 * v.get("SQ_INSTS_VALU_FLOPS_FP32", 0.0)
+        t = ms[form] * 1e-3
+        issue = v["SQ_INSTS_VALU"] / t / (256 * 2.4e9)
+        rec[form] = dict(push_ms=ms[form], fp64_flop_per_step=f64 / steps,
+                         fp32_flop_per_step=f32 / steps, valu_issue_frac=issue,
+                         fp64_tflops=f64 / t / 1e12, fp32_tflops=f32 / t / 1e12,
+                         fp64_arith_frac=(v.get("SQ_INSTS_VALU_FMA_F64", 0) + v.get(
+                             "SQ_INSTS_VALU_MUL_F64", 0) + v.get("SQ_INSTS_VALU_ADD_F64", 0))
+                         / v["SQ_INSTS_VALU"])
+        r = rec[form]
+        md.append(f"- {form}: {r['fp64_flop_per_step']:.0f} FP64 + {r['fp32_flop_per_step']:.0f} "
+                  f"FP32 FLOPs per electron-step; {r['fp64_tflops']:.1f} TFLOP/s FP64 + "
+                  f"{r['fp32_tflops']:.1f} TFLOP/s FP32 in {ms[form]:.1f} ms; VALU issue "
+                  f"{100 * issue:.0f}% of 256 CU x 2.4 GHz; FP64 add/mul/fma are "
+                  f"{100 * r['fp64_arith_frac']:.0f}% of VALU instructions.")
+    md += ["", f"Kernel source hash {kernel_source_hash()} (bench.py uses these figures only for",
+           "that build of the push kernels)."]
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    with open(out_json.replace(".json", ".md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(json.dumps(rec))
+    return rec
+
+
+def _counter_record():
+    try:
+        rec = json.load(open(PROFILE_COUNTERS_FILE))
+        return rec if rec.get("kernel_source_hash") == kernel_source_hash() else None
+    except (OSError, ValueError):
+        return None
+
+
 def main():
     if len(sys.argv) == 4 and sys.argv[1] == "--traffic-from":
         write_traffic_summary(sys.argv[2], sys.argv[3])
+        return
+    if len(sys.argv) == 4 and sys.argv[1] == "--counters-from":
+        write_counter_summary(sys.argv[2], sys.argv[3])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +429,20 @@ def main():
             mean_energy_rel_err=float((Kmx.double().mean() / K64.double().mean() - 1).item()),
             same_direction=float((f64 == fmx).double().mean().item()),
         )
+        crec = _counter_record()
+        if crec is not None:
+            # FLOPs per electron-step of the mixed form from the counter run
+            f32 = crec["mixed"]["fp32_flop_per_step"] * steps / (mix_ms * 1e-3) / 1e12
+            f64m = crec["mixed"]["fp64_flop_per_step"] * steps / (mix_ms * 1e-3) / 1e12
+            mixed["roofline"] = {
+                "bound": "alu", "achieved_fp32": f32, "achieved_fp64": f64m,
+                "peak_fp32": FP32_VECTOR_PEAK_TFLOPS, "peak_fp64": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s",
+                "frac": f32 / FP32_VECTOR_PEAK_TFLOPS + f64m / FP64_VECTOR_PEAK_TFLOPS,
+                "flop_per_electron_step": {"fp32": crec["mixed"]["fp32_flop_per_step"],
+                                           "fp64": crec["mixed"]["fp64_flop_per_step"]},
+                "note": "frac = FP32 share of the published FP32 peak (packed, two-wide) + FP64 "
+                        "share of the FP64 peak; the build uses one-wide FP32 only"}
         log(f"mixed: {mixed}")
 
     adaptive = None
@@ -429,6 +525,8 @@ def main():
             "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
             "flop_per_electron_step": ALGO_FLOP_PER_STEP, "push_ms": round(push_avg, 2),
+            "flop_per_electron_step_counters": (None if _counter_record() is None else
+                                                _counter_record()["fp64"]["fp64_flop_per_step"]),
         },
         "push_electron_steps_per_s": push_rate,
         "ionize_ms": round(ion_avg, 2),

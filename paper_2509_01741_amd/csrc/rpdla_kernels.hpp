@@ -78,9 +78,8 @@ __global__ void __launch_bounds__(256) birth_phase_kernel(
 // window start; state s (charge state k_first + s) accumulates GL-4 panel
 // integrals of its rate from the previous birth; at the panel where the sum
 // reaches the Exp(1) threshold the crossing is solved by bracketed Newton.
-// Panels where the rate bound proves w = 0 at every node (the rate is set to
-// exactly zero below lnw_zero) are skipped: before the first state's
-// possible window and after the current state's window.
+// Panels where a rigorous bound keeps the rate negligible at every node are
+// skipped: before each state's possible window and after it.
 // ---------------------------------------------------------------------------
 template <int FIELD, class CFG>
 __device__ inline double emag2_f64(const CFG& c, double X, double Y, double Z, double tau)
@@ -90,40 +89,116 @@ __device__ inline double emag2_f64(const CFG& c, double X, double Y, double Z, d
     return ax * ax + ay * ay + az * az;
 }
 
+// The field of an atom at rest reduced to its time dependence.  For the RP
+// models every term of the series is g e^{i Psi} q^n times a polynomial in
+// rho^2, so  Er/r ~ g Re(e^{i Psi} A_E),  Ez = g Im(e^{i Psi} A_Z)  with the
+// complex position factors A_E = q^2 P_E(q), A_Z = q^2 P_Z(q) (the push's
+// series coefficients regrouped by powers of q), g = a0 exp(-rho^2/D - s^2)
+// and Psi = tau + psi_c: one sine/cosine and one exponential per time.
+struct AtomGeom {
+    double X, Y, Z;
+    double r2, mrD, psi_c;
+    double aer, aei, azr, azi;
+};
+
 template <int FIELD, class CFG>
-__device__ inline double rate_at(const CFG& c, const AdkState& st, double X, double Y, double Z,
-                                 double tau)
+__device__ inline AtomGeom atom_geom(const CFG& c, double X, double Y, double Z)
 {
-    return adk_rate_n(st, emag2_f64<FIELD>(c, X, Y, Z, tau));
+    AtomGeom a{X, Y, Z, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (FIELD == 1 || FIELD == 3 || FIELD == 5) {
+        const double r2 = (X * X + Y * Y) * c.inv_w0n2;
+        const double zeta = Z * c.inv_zrn;
+        const double iD = 1.0 / (1.0 + zeta * zeta);
+        const double rD = r2 * iD;
+        a.r2 = r2;
+        a.mrD = -rD;
+        a.psi_c = c.phi0 - Z - rD * zeta;
+        const Cx<double> q{iD, zeta * iD};
+        const double r4 = r2 * r2, r6 = r4 * r2, r8 = r4 * r4;
+        // P_E(q) = sum p_n q^n and P_Z(q) = sum z_n q^n, by Horner in q
+        // Horner step: p <- p q + coefficient
+        auto horner = [&q](Cx<double> p, double coef) {
+            const Cx<double> t = cmul(p, q);
+            return Cx<double>{t.re + coef, t.im};
+        };
+        Cx<double> pe{1.0, 0.0}, pz{c.eps, 0.0};
+        if constexpr (FIELD == 1) {
+            pz = horner(Cx<double>{-c.eps * r2, 0.0}, c.eps);
+        } else {
+            double p[7] = {1.0, -0.5 * c.e2, c.e2 * r2, -0.25 * c.e2 * r4, 0.0, 0.0, 0.0};
+            if constexpr (FIELD == 5) {
+                p[2] += -0.375 * c.e4;
+                p[3] += -0.375 * c.e4 * r2;
+                p[4] = 1.0625 * c.e4 * r4;
+                p[5] = -0.375 * c.e4 * r6;
+                p[6] = 0.03125 * c.e4 * r8;
+            }
+            const double z[5] = {c.eps, -c.eps * r2 + 0.5 * c.e3, 0.5 * c.e3 * r2,
+                                 -1.25 * c.e3 * r4, 0.25 * c.e3 * r6};
+            constexpr int NE = (FIELD == 5) ? 7 : 4;
+            pe = Cx<double>{p[NE - 1], 0.0};
+#pragma unroll
+            for (int n = NE - 2; n >= 0; --n) pe = horner(pe, p[n]);
+            pz = Cx<double>{z[4], 0.0};
+#pragma unroll
+            for (int n = 3; n >= 0; --n) pz = horner(pz, z[n]);
+        }
+        const Cx<double> q2 = cmul(q, q);
+        const Cx<double> ae = cmul(q2, pe), az = cmul(q2, pz);
+        a.aer = ae.re; a.aei = ae.im; a.azr = az.re; a.azi = az.im;
+    }
+    return a;
+}
+
+template <int FIELD, class CFG>
+__device__ inline double emag2_atom(const CFG& c, const AtomGeom& a, double tau)
+{
+    if constexpr (FIELD == 1 || FIELD == 3 || FIELD == 5) {
+        const double s = (tau - a.Z) * c.inv_T0n;
+        const double g = c.a0 * fm::exp_f64(a.mrD - s * s);
+        double sn, cs;
+        fm::sincos_f64(tau + a.psi_c, &sn, &cs);
+        const double et = c.er_scale * g * (cs * a.aer - sn * a.aei);
+        const double ez = c.ez_scale * g * (sn * a.azr + cs * a.azi);
+        return et * et * a.r2 + ez * ez;
+    } else {
+        return emag2_f64<FIELD>(c, a.X, a.Y, a.Z, tau);
+    }
+}
+
+template <int FIELD, class CFG>
+__device__ inline double rate_at(const CFG& c, const AdkState& st, const AtomGeom& a, double tau)
+{
+    return adk_rate_n(st, emag2_atom<FIELD>(c, a, tau));
 }
 
 // GL-4 estimate of the integral of the rate over [a, b]; the nodes are
 // evaluated one after another (one field evaluation live at a time).
 template <int FIELD, class CFG>
-__device__ inline double gl4_integral(const CFG& c, const AdkState& st, double X, double Y,
-                                      double Z, double a, double b)
+__device__ inline double gl4_integral(const CFG& c, const AdkState& st, const AtomGeom& ag,
+                                      double a, double b)
 {
     const double h = 0.5 * (b - a), m = 0.5 * (a + b);
     double acc = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < 4; ++i) acc += c.gl_w[i] * rate_at<FIELD>(c, st, X, Y, Z, m + h * c.gl_x[i]);
+    for (int i = 0; i < 4; ++i) acc += c.gl_w[i] * rate_at<FIELD>(c, st, ag, m + h * c.gl_x[i]);
     return h * acc;
 }
 
 template <int FIELD, class CFG>
-__device__ double solve_crossing(const CFG& c, const AdkState& st, double X, double Y, double Z,
-                                 double lo, double hi, double target, double Ghi)
+__device__ double solve_crossing(const CFG& c, const AdkState& st, const AtomGeom& ag, double lo,
+                                 double hi, double target, double Ghi)
 {
     if (!(target > 0.0)) return lo;
     double tl = lo, th = hi;
     double t = lo + (hi - lo) * (target / Ghi);
     if (!(t > tl && t < th)) t = 0.5 * (tl + th);
     for (int it = 0; it < 100; ++it) {
-        const double gd = gl4_integral<FIELD>(c, st, X, Y, Z, lo, t) - target;
+        const double gd = gl4_integral<FIELD>(c, st, ag, lo, t) - target;
         if (gd == 0.0) return t;
         if (gd > 0.0) th = t; else tl = t;
         const double tol = ldexp(fmax(fabs(t), kTwoPi), -40);
-        const double w = rate_at<FIELD>(c, st, X, Y, Z, t);
+        const double w = rate_at<FIELD>(c, st, ag, t);
         double tn = __builtin_nan("");
         if (w > 0.0) {
             const double dlt = gd / w;
@@ -168,6 +243,7 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
     const int64_t M = (int64_t)ceil((tau_e - tau_s) / h);
     const double b2 = bound2_f64<FIELD>(c, X, Y, Z);
     const double Zc = Z;  // the envelope peaks at tau = Z for the pulse models
+    const AtomGeom ag = atom_geom<FIELD>(c, X, Y, Z);
 
     int s = 0;
     double target = -log(uniform_j(seed, cfg, atom, k_first + 2));
@@ -190,9 +266,9 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
         bool done = false;
         while (true) {
             const double lo = (tstart > a) ? tstart : a;
-            const double seg = gl4_integral<FIELD>(c, st, X, Y, Z, lo, b);
+            const double seg = gl4_integral<FIELD>(c, st, ag, lo, b);
             if (I + seg < target) { I += seg; break; }
-            const double t = solve_crossing<FIELD>(c, st, X, Y, Z, lo, b, target - I, seg);
+            const double t = solve_crossing<FIELD>(c, st, ag, lo, b, target - I, seg);
             out[s] = t * c.inv_omega;
             ++s;
             if (s >= K) { done = true; break; }

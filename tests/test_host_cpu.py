@@ -73,3 +73,31 @@ def test_experiment_reductions():
     assert math.isnan(ex.phase_near_zero_fraction(pr, 0, math.pi / 4))
     assert ex.radius_quantile(pr, 1, 4e-6, 0.9) == 4e-6   # 60% in the last radius bin
     assert ex.radius_quantile(pr, 1, 4e-6, 0.3) == 1e-6
+
+
+def test_counter_summary_arithmetic(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    f64 = "void rpdla::push_kernel<5, rpdla::ElecF64>(rpdla::DevCfg, rpdla::PushIO)"
+    mix = "void rpdla::push_kernel<5, rpdla::ElecMixed>(rpdla::DevCfg, rpdla::PushIO)"
+    d = tmp_path / "S"
+    d.mkdir()
+    with open(d / "run_counter_collection.csv", "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for k, vals in ((f64, dict(SQ_INSTS_VALU=600.0, SQ_INSTS_VALU_FLOPS_FP64=1000.0,
+                                    SQ_INSTS_VALU_FMA_F64=300.0, SQ_INSTS_VALU_MUL_F64=100.0,
+                                    SQ_INSTS_VALU_ADD_F64=50.0)),
+                        (mix, dict(SQ_INSTS_VALU=400.0, SQ_INSTS_VALU_FLOPS_FP64=100.0,
+                                   SQ_INSTS_VALU_FLOPS_FP32=500.0))):
+            for ctr, v in vals.items():
+                f.write(f'0,"{k}",{ctr},{v}\n')
+    bj = tmp_path / "b.json"
+    bj.write_text("noise\n" + json.dumps({"config": {"electron_steps": 64.0},
+                                         "roofline": {"push_ms": 1000.0},
+                                         "mixed": {"push_ms": 500.0}}) + "\n")
+    rec = bench.write_counter_summary(str(d), str(bj), out_json=str(tmp_path / "c.json"))
+    assert rec["fp64"]["fp64_flop_per_step"] == 1000.0          # 64 lanes x 1000 / 64 steps
+    assert rec["mixed"]["fp32_flop_per_step"] == 500.0
+    assert rec["mixed"]["fp64_flop_per_step"] == 100.0
+    assert abs(rec["fp64"]["fp64_arith_frac"] - 450.0 / 600.0) < 1e-15
+    assert abs(rec["fp64"]["valu_issue_frac"] - 600.0 / (256 * 2.4e9)) < 1e-24
