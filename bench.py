@@ -31,8 +31,9 @@ C_LIGHT = 299792458.0
 # polynomial implementations): 4 x (223 field + 27 Lorentz) + 85 RK4 = 1085.
 ALGO_FLOP_PER_STEP = 1085.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
-# FP32 vector peak as published (it counts packed two-wide FP32 operations;
-# this build compiles without packed FP32, so one-wide FP32 peaks at 78.6)
+# FP32 vector peak: a wave64 FP32 instruction takes half the cycles of an
+# FP64 one (the mixed push reaches 97 TFLOP/s FP32 with no packed FP32
+# instructions, which this build does not emit)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 PROFILE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "push_rp_ne_fp64_100k_counters.json")
 COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32",
@@ -277,7 +278,7 @@ def write_counter_summary(counter_dir, bench_json, out_json=PROFILE_COUNTERS_FIL
         t = ms[form] * 1e-3
         issue = v["SQ_INSTS_VALU"] / t / (256 * 2.4e9)
         rec[form] = dict(push_ms=ms[form], fp64_flop_per_step=f64 / steps,
-                         fp32_flop_per_step=f32 / steps, valu_issue_frac=issue,
+                         fp32_flop_per_step=f32 / steps, valu_per_cu_cycle=issue,
                          fp64_tflops=f64 / t / 1e12, fp32_tflops=f32 / t / 1e12,
                          fp64_arith_frac=(v.get("SQ_INSTS_VALU_FMA_F64", 0) + v.get(
                              "SQ_INSTS_VALU_MUL_F64", 0) + v.get("SQ_INSTS_VALU_ADD_F64", 0))
@@ -285,10 +286,13 @@ def write_counter_summary(counter_dir, bench_json, out_json=PROFILE_COUNTERS_FIL
         r = rec[form]
         md.append(f"- {form}: {r['fp64_flop_per_step']:.0f} FP64 + {r['fp32_flop_per_step']:.0f} "
                   f"FP32 FLOPs per electron-step; {r['fp64_tflops']:.1f} TFLOP/s FP64 + "
-                  f"{r['fp32_tflops']:.1f} TFLOP/s FP32 in {ms[form]:.1f} ms; VALU issue "
-                  f"{100 * issue:.0f}% of 256 CU x 2.4 GHz; FP64 add/mul/fma are "
-                  f"{100 * r['fp64_arith_frac']:.0f}% of VALU instructions.")
-    md += ["", f"Kernel source hash {kernel_source_hash()} (bench.py uses these figures only for",
+                  f"{r['fp32_tflops']:.1f} TFLOP/s FP32 in {ms[form]:.1f} ms; "
+                  f"{issue:.2f} VALU wave instructions per CU per cycle (256 CU x 2.4 GHz); "
+                  f"FP64 add/mul/fma are {100 * r['fp64_arith_frac']:.0f}% of VALU instructions.")
+    md += ["", "A wave64 FP64 instruction occupies its SIMD for 4 cycles and an FP32 one for 2, so",
+           "the ceiling is 1.0 wave instruction per CU per cycle for FP64 code and 2.0 for FP32 code",
+           "(the FP64 and FP32 vector peaks, 78.6 and 157.3 TFLOP/s with fused multiply-adds).", "",
+           f"Kernel source hash {kernel_source_hash()} (bench.py uses these figures only for",
            "that build of the push kernels)."]
     with open(out_json, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -441,8 +445,8 @@ def main():
                 "frac": f32 / FP32_VECTOR_PEAK_TFLOPS + f64m / FP64_VECTOR_PEAK_TFLOPS,
                 "flop_per_electron_step": {"fp32": crec["mixed"]["fp32_flop_per_step"],
                                            "fp64": crec["mixed"]["fp64_flop_per_step"]},
-                "note": "frac = FP32 share of the published FP32 peak (packed, two-wide) + FP64 "
-                        "share of the FP64 peak; the build uses one-wide FP32 only"}
+                "note": "frac = FP32 share of the FP32 vector peak + FP64 share of the FP64 "
+                        "vector peak (both kinds of instruction share the SIMDs)"}
         log(f"mixed: {mixed}")
 
     adaptive = None

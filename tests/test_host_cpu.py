@@ -100,4 +100,4 @@ def test_counter_summary_arithmetic(tmp_path):
     assert rec["mixed"]["fp32_flop_per_step"] == 500.0
     assert rec["mixed"]["fp64_flop_per_step"] == 100.0
     assert abs(rec["fp64"]["fp64_arith_frac"] - 450.0 / 600.0) < 1e-15
-    assert abs(rec["fp64"]["valu_issue_frac"] - 600.0 / (256 * 2.4e9)) < 1e-24
+    assert abs(rec["fp64"]["valu_per_cu_cycle"] - 600.0 / (256 * 2.4e9)) < 1e-24
