@@ -33,7 +33,7 @@ ALGO_FLOP_PER_STEP = 1085.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # FP32 vector peak: a wave64 FP32 instruction takes half the cycles of an
 # FP64 one (the mixed push reaches 97 TFLOP/s FP32 with no packed FP32
-# instructions, which this build does not emit)
+# instructions: the kernels are compiled without them)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 PROFILE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "push_rp_ne_fp64_100k_counters.json")
 COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32",
