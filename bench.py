@@ -140,7 +140,8 @@ def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk):
                 configs=n_cfg, atoms_per_cfg=atoms_per_cfg, atoms_per_chunk=atoms_per_chunk,
                 chunks=-(-atoms_per_cfg // atoms_per_chunk), ms=round(ms, 2),
                 electron_steps=n_steps, electron_steps_per_s=n_steps / (ms * 1e-3),
-                born=int(tal[0] + tal[1]), backward_fraction_min_max=[float(bwd.min()), float(bwd.max())])
+                born=int(tal[0] + tal[1]), backward_fraction_min_max=[float(bwd.min()), float(bwd.max())],
+                occupancy=occupancy(2, int(wl["field_order"]), precision))
 
 
 PUSH_KERNEL_NAME = "push_kernel<5, rpdla::ElecF64>"
@@ -303,6 +304,15 @@ def write_counter_summary(counter_dir, bench_json, out_json=PROFILE_COUNTERS_FIL
     return rec
 
 
+def occupancy(kind, field, precision):
+    """Registers and resident waves per SIMD of a kernel (None if the query fails)."""
+    try:
+        from paper_2509_01741_amd import binding as B
+        return B.rpdla_kernel_occupancy(kind, field, precision)
+    except Exception:
+        return None
+
+
 def _counter_record():
     try:
         rec = json.load(open(PROFILE_COUNTERS_FILE))
@@ -445,8 +455,10 @@ def main():
                 "frac": f32 / FP32_VECTOR_PEAK_TFLOPS + f64m / FP64_VECTOR_PEAK_TFLOPS,
                 "flop_per_electron_step": {"fp32": crec["mixed"]["fp32_flop_per_step"],
                                            "fp64": crec["mixed"]["fp64_flop_per_step"]},
+                "valu_per_cu_cycle": crec["mixed"]["valu_per_cu_cycle"],
                 "note": "frac = FP32 share of the FP32 vector peak + FP64 share of the FP64 "
                         "vector peak (both kinds of instruction share the SIMDs)"}
+        mixed["occupancy"] = occupancy(0, int(ens.L.field), B.RPDLA_MIXED)
         log(f"mixed: {mixed}")
 
     adaptive = None
@@ -531,6 +543,12 @@ def main():
             "flop_per_electron_step": ALGO_FLOP_PER_STEP, "push_ms": round(push_avg, 2),
             "flop_per_electron_step_counters": (None if _counter_record() is None else
                                                 _counter_record()["fp64"]["fp64_flop_per_step"]),
+            # issue rate from the counter run (ceiling 1.0 for FP64 code), the
+            # kernel's registers and resident waves, HBM rate from the traffic
+            "valu_per_cu_cycle": (None if _counter_record() is None else
+                                  _counter_record()["fp64"]["valu_per_cu_cycle"]),
+            "occupancy": occupancy(0, int(ens.L.field), B.RPDLA_FP64),
+            "hbm_gb_s": None if traffic is None else traffic / (push_avg * 1e-3) / 1e9,
         },
         "push_electron_steps_per_s": push_rate,
         "ionize_ms": round(ion_avg, 2),

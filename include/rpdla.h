@@ -377,6 +377,18 @@ rpdla_status rpdla_set_launch_shape(int32_t kernel, int32_t field, int32_t preci
 rpdla_status rpdla_get_launch_shape(int32_t kernel, int32_t field, int32_t precision,
                                     int32_t* block, int32_t* grid_factor);
 
+/* Resources and occupancy of one kernel (kinds as above; field 1, 3, 5, 10 or
+ * 11; precision RPDLA_FP64 or RPDLA_MIXED, ignored for ionize) on the current
+ * device, at its current launch shape: vector registers per lane (*vgprs),
+ * private scratch bytes per lane (*scratch_bytes, nonzero only when registers
+ * spill) and resident waves per SIMD (*waves_per_simd, from the runtime's
+ * occupancy query; a CU has four SIMDs).  The batched push is sized with the
+ * LDS table of 64 configurations.  Host pointers, all non-NULL; RPDLA_EINVAL
+ * otherwise, RPDLA_EHIP when the runtime query fails. */
+rpdla_status rpdla_kernel_occupancy(int32_t kernel, int32_t field, int32_t precision,
+                                    int32_t* vgprs, int32_t* scratch_bytes,
+                                    double* waves_per_simd);
+
 /* Status text and the calling thread's last error detail (never NULL). */
 const char* rpdla_status_string(rpdla_status s);
 const char* rpdla_last_error(void);

@@ -102,6 +102,8 @@ def _load():
         "rpdla_autotune": (i32, [LP, i32, i64, i32, i32, C.c_char_p, C.c_size_t, vp]),
         "rpdla_set_launch_shape": (i32, [i32, i32, i32, i32, i32]),
         "rpdla_get_launch_shape": (i32, [i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "rpdla_kernel_occupancy": (i32, [i32, i32, i32, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "rpdla_status_string": (C.c_char_p, [i32]),
         "rpdla_last_error": (C.c_char_p, []),
         "rpdla_version": (C.c_char_p, []),
@@ -343,6 +345,15 @@ def rpdla_get_launch_shape(kernel, field, precision):
     _check(lib.rpdla_get_launch_shape(kernel, field, precision, C.byref(b), C.byref(g)),
            "rpdla_get_launch_shape")
     return b.value, g.value
+
+
+def rpdla_kernel_occupancy(kernel, field, precision) -> dict:
+    """Vector registers, scratch bytes per lane and resident waves per SIMD of
+    one kernel at its current launch shape (device query)."""
+    v, s, w = C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib.rpdla_kernel_occupancy(kernel, field, precision, C.byref(v), C.byref(s), C.byref(w)),
+           "rpdla_kernel_occupancy")
+    return {"vgprs": v.value, "scratch_bytes": s.value, "waves_per_simd": w.value}
 
 
 def rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last) -> int:

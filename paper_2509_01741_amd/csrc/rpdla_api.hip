@@ -980,3 +980,59 @@ rpdla_status rpdla_histogram2d(int64_t n, const double* a, const double* b, cons
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Kernel resources and occupancy
+// ===========================================================================
+namespace {
+
+template <typename K>
+rpdla_status kernel_info(K kern, int block, size_t lds, int32_t* vgprs, int32_t* scratch,
+                         double* waves)
+{
+    hipFuncAttributes fa;
+    RPDLA_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)));
+    int per_cu = 0;
+    RPDLA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds));
+    *vgprs = fa.numRegs;
+    *scratch = (int32_t)fa.localSizeBytes;
+    *waves = (double)per_cu * (double)(block / 64) / 4.0;   // four SIMDs per CU
+    return RPDLA_OK;
+}
+
+template <int FIELD>
+rpdla_status field_kernel_info(int kind, bool mixed, int32_t* v, int32_t* s, double* w)
+{
+    const Shape sh = get_shape(kind, FIELD, kind == kKindIonize ? 0 : (mixed ? 1 : 0));
+    if (kind == kKindIonize)
+        return kernel_info(rpdla::ionize_kernel<FIELD>, sh.block, 0, v, s, w);
+    if (kind == kKindPush)
+        return mixed ? kernel_info(rpdla::push_kernel<FIELD, rpdla::ElecMixed>, sh.block, 0, v, s, w)
+                     : kernel_info(rpdla::push_kernel<FIELD, rpdla::ElecF64>, sh.block, 0, v, s, w);
+    const size_t lds = (size_t)rpdla::kMaxCfg * (sizeof(rpdla::PushCfg) + sizeof(unsigned long long));
+    return mixed ? kernel_info(rpdla::batch_push_kernel<FIELD, rpdla::ElecMixed>, sh.block, lds, v, s, w)
+                 : kernel_info(rpdla::batch_push_kernel<FIELD, rpdla::ElecF64>, sh.block, lds, v, s, w);
+}
+
+}  // namespace
+
+extern "C" {
+
+rpdla_status rpdla_kernel_occupancy(int32_t kernel, int32_t field, int32_t precision, int32_t* vgprs,
+                                    int32_t* scratch_bytes, double* waves_per_simd)
+{
+    if (!vgprs || !scratch_bytes || !waves_per_simd) return fail(RPDLA_EINVAL, "null pointer");
+    if (kernel < 0 || kernel > 2) return fail(RPDLA_EINVAL, "kernel must be 0 (push), 1 (ionize) or 2 (batched push)");
+    if (!(precision == RPDLA_FP64 || precision == RPDLA_MIXED)) return fail(RPDLA_EINVAL, "unknown precision");
+    const bool mixed = precision == RPDLA_MIXED;
+    switch (field) {
+    case 1: return field_kernel_info<1>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
+    case 3: return field_kernel_info<3>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
+    case 5: return field_kernel_info<5>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
+    case 10: return field_kernel_info<10>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
+    case 11: return field_kernel_info<11>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
+    default: return fail(RPDLA_EINVAL, "unknown field model %d", field);
+    }
+}
+
+}  // extern "C"

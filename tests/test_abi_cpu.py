@@ -120,6 +120,17 @@ def test_validation_without_gpu():
     assert lib.rpdla_autotune(C.byref(L), 0, 10, 1, 10, None, 0, p) == B.RPDLA_ERANGE
 
 
+def test_kernel_occupancy_validation():
+    from paper_2509_01741_amd import binding as B
+    lib = B.lib
+    v, sc, w = C.c_int32(), C.c_int32(), C.c_double()
+    ok = (C.byref(v), C.byref(sc), C.byref(w))
+    assert lib.rpdla_kernel_occupancy(0, 5, 0, None, C.byref(sc), C.byref(w)) == B.RPDLA_EINVAL
+    assert lib.rpdla_kernel_occupancy(3, 5, 0, *ok) == B.RPDLA_EINVAL
+    assert lib.rpdla_kernel_occupancy(0, 2, 0, *ok) == B.RPDLA_EINVAL
+    assert lib.rpdla_kernel_occupancy(0, 5, 2, *ok) == B.RPDLA_EINVAL
+
+
 def test_ne_table_matches_oracle(orc):
     """Both sides carry their own copy of the neon potentials; they must agree."""
     src = open(os.path.join(ROOT, "paper_2509_01741_amd", "csrc", "rpdla_api.hip")).read()

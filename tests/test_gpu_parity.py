@@ -260,6 +260,21 @@ def test_autotune_and_shape_independence(env):
             assert np.array_equal(a, b, equal_nan=True)
 
 
+def test_kernel_occupancy(env):
+    """The push and ionize kernels keep every value in registers (no scratch)
+    and reach the resident waves their launch bounds ask for."""
+    torch, B, O = env
+    want = {(B.RPDLA_KERNEL_PUSH, B.RPDLA_FP64): 4, (B.RPDLA_KERNEL_PUSH, B.RPDLA_MIXED): 6,
+            (B.RPDLA_KERNEL_IONIZE, B.RPDLA_FP64): 3, (B.RPDLA_KERNEL_BATCHED_PUSH, B.RPDLA_FP64): 4,
+            (B.RPDLA_KERNEL_BATCHED_PUSH, B.RPDLA_MIXED): 6}
+    for (kind, prec), waves in want.items():
+        r = B.rpdla_kernel_occupancy(kind, 5, prec)
+        print(f"[occupancy] kind {kind} precision {prec}: {r}")
+        assert 0 < r["vgprs"] <= 512 // waves
+        assert r["scratch_bytes"] == 0
+        assert r["waves_per_simd"] >= waves
+
+
 def test_epilogue_parity(env):
     torch, B, O = env
     n = 5000
