@@ -101,3 +101,40 @@ def test_counter_summary_arithmetic(tmp_path):
     assert rec["mixed"]["fp64_flop_per_step"] == 100.0
     assert abs(rec["fp64"]["fp64_arith_frac"] - 450.0 / 600.0) < 1e-15
     assert abs(rec["fp64"]["valu_per_cu_cycle"] - 600.0 / (256 * 2.4e9)) < 1e-24
+
+
+def test_fp64_vs_oracle_statistics():
+    """bench.py's FP64-vs-oracle statistic: identical inputs give full
+    agreement; a planted 1e-6 energy error in one electron is counted."""
+    import types
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle as O
+    from paper_2509_01741_amd import workloads
+
+    wl = workloads.FULL_FP64
+    rec = wl["lasers"][0]
+    OL = O.laser_intensity(rec["lam"], rec["w0"], rec["tau"], rec["I"])
+    K = wl["k_last"] - wl["k_first"] + 1
+    na = 3
+    x, y, z = O.sample_atoms(wl["seed"], wl["cfg_id"], 0, na, wl["r_factor"] * OL.w0,
+                             O.rayleigh(OL))
+    t = O.ionize(OL, wl["seed"], wl["cfg_id"], 0, x, y, z, wl["k_first"], wl["k_last"])
+    out = O.push(OL, t, x, y, z, K)
+    ens = types.SimpleNamespace(tb=torch.from_numpy(t.copy()),
+                                out=tuple(torch.from_numpy(o.copy()) for o in out))
+    r = bench.fp64_vs_oracle(ens, OL, K, (x, y, z, t, out))
+    born = int(np.isfinite(t).sum())
+    assert r["electrons"] == born and r["born_mismatch"] == 0
+    assert r["energy_frac_le_1e8"] == 1.0 and r["same_direction"] == 1.0
+    assert r["birth_time_max_rel"] == 0.0 and r["ill_conditioned"] == 0
+    j = int(np.nonzero(np.isfinite(t))[0][0])
+    bad = [o.copy() for o in out]
+    bad[0][j] *= 1.0 + 1e-6
+    ens.out = tuple(torch.from_numpy(o) for o in bad)
+    r = bench.fp64_vs_oracle(ens, OL, K, (x, y, z, t, out))
+    assert r["energy_frac_le_1e8"] == (born - 1) / born
