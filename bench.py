@@ -158,6 +158,47 @@ def fp64_vs_oracle(ens, OL, K, sample):
                      "moves by more than 1e-10 when the birth time moves by 1e-15 relative")
 
 
+def measure_mixed_workload(wl):
+    """FP64 and mixed push of one full single-laser ensemble (the mixed form's
+    own workload: 1 PW into w0 = 1.5 um): times, speedup, mixed-vs-FP64
+    energy errors."""
+    import torch
+    from paper_2509_01741_amd import binding as B
+    from paper_2509_01741_amd import pipeline
+    ens = pipeline.Ensemble(wl, precision=B.RPDLA_FP64)
+    ens.sample()
+    ens.ionize()
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    outs = tuple(torch.empty_like(o) for o in ens.out)
+    a, b, c = ev(), ev(), ev()
+    a.record()
+    B.rpdla_push(ens.L, B.RPDLA_FP64, ens.tb, ens.x, ens.y, ens.z, ens.K, ens.out)
+    b.record()
+    B.rpdla_push(ens.L, B.RPDLA_MIXED, ens.tb, ens.x, ens.y, ens.z, ens.K, outs)
+    c.record()
+    torch.cuda.synchronize()
+    ms64, msmx = a.elapsed_time(b), b.elapsed_time(c)
+    steps, born = electron_steps(ens.tb, ens.z, ens.K, ens.L)
+    fin = torch.isfinite(ens.tb)
+
+    def kin(o):
+        u2 = o[0][fin] ** 2 + o[1][fin] ** 2 + o[2][fin] ** 2
+        return 0.51099895 * u2 / (torch.sqrt(1 + u2) + 1), o[2][fin] > 0
+
+    K64, f64 = kin(ens.out)
+    Kmx, fmx = kin(outs)
+    rel = (Kmx - K64).abs() / K64
+    return dict(workload=wl["name"], atoms=ens.n, born_electrons=born, electron_steps=steps,
+                fp64_push_ms=round(ms64, 2), mixed_push_ms=round(msmx, 2),
+                fp64_electron_steps_per_s=steps / (ms64 * 1e-3),
+                mixed_electron_steps_per_s=steps / (msmx * 1e-3), speedup=ms64 / msmx,
+                frac_rel_err_le_1e3=float((rel <= 1e-3).double().mean().item()),
+                median_rel_err=float(rel.median().item()),
+                mean_energy_rel_err=float((Kmx.double().mean() / K64.double().mean() - 1).item()),
+                same_direction=float((f64 == fmx).double().mean().item()))
+
+
 def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk):
     """One timed batched sweep (after an untimed one that captures the graph)
     on a side stream; electron-steps counted by the library."""
@@ -512,6 +553,10 @@ def main():
                         "vector peak (both kinds of instruction share the SIMDs)"}
         mixed["occupancy"] = occupancy(0, int(ens.L.field), B.RPDLA_MIXED)
         log(f"mixed: {mixed}")
+
+    if mixed is not None:
+        mixed["workload_1pw"] = measure_mixed_workload(workloads.MIXED_AB)
+        log(f"mixed, 1 PW workload: {mixed['workload_1pw']}")
 
     adaptive = None
     if not args.no_adaptive:
