@@ -89,8 +89,10 @@ def test_counter_summary_arithmetic(tmp_path):
                                     SQ_INSTS_VALU_ADD_F64=50.0)),
                         (mix, dict(SQ_INSTS_VALU=400.0, SQ_INSTS_VALU_FLOPS_FP64=100.0,
                                    SQ_INSTS_VALU_FLOPS_FP32=500.0))):
-            for ctr, v in vals.items():
-                f.write(f'0,"{k}",{ctr},{v}\n')
+            # the mixed push is dispatched twice (untimed, then timed): one counts
+            for disp in ((0,) if k == f64 else (1, 2)):
+                for ctr, v in vals.items():
+                    f.write(f'{disp},"{k}",{ctr},{v}\n')
     bj = tmp_path / "b.json"
     bj.write_text("noise\n" + json.dumps({"config": {"electron_steps": 64.0},
                                          "roofline": {"push_ms": 1000.0},
