@@ -563,7 +563,9 @@ def main():
         mixed["occupancy"] = occupancy(0, int(ens.L.field), B.RPDLA_MIXED)
         log(f"mixed: {mixed}")
 
-    if mixed is not None:
+    if mixed is not None and args.atoms is None:
+        # full-size runs only: counter runs at a reduced size read the last
+        # push launches, which must stay those of the benchmark ensemble
         mixed["workload_1pw"] = measure_mixed_workload(workloads.MIXED_AB)
         log(f"mixed, 1 PW workload: {mixed['workload_1pw']}")
 
