@@ -28,8 +28,14 @@
  *   - controlled-step fifth-order push .......... Sec. 1 and Sec. 2.1
  *
  * Readings where the paper is silent or garbled are listed next to the code
- * that takes them.  Parity status of every function: pinned by the CPU tests
- * (closed forms, invariants, library routines, printed worked values).
+ * that takes them.  Parity status: every function is pinned by the CPU tests
+ * (closed forms, invariants, library routines, printed worked values) except
+ * one part of the tunnelling rate, which is PARITY UNPINNED: the dependence of
+ * its prefactor C^2 on a non-integer effective quantum number n*.  The paper
+ * names the tunnelling model without a formula, so nothing fixes that
+ * dependence; the pins cover the hydrogen and hydrogen-like limits (n* = 1),
+ * the state -> (potential, charge) mapping through the hydrogen-like last
+ * neon electron, and the power of the field at every neon n*.
  */
 #include <math.h>
 #include <stdint.h>
@@ -300,7 +306,8 @@ void orc_field(const orc_laser* L, double x, double y, double z, double t,
  *   w = C^2 Ip (2 F0/F)^(2 n* - 1) exp(-2 F0 / (3 F)),
  *   n* = Z / sqrt(2 Ip), F0 = (2 Ip)^(3/2), C^2 = 2^(2 n*) / (n* Gamma(2 n*)),
  * Z the charge after ionization, evaluated in log space.  The rate is set to
- * exactly zero when F = 0 or ln(w [1/s]) < -700.
+ * exactly zero when F = 0 or ln(w [1/s]) < -700.  Parity unpinned: the n*
+ * dependence of C^2 (see the header of this file).
  * ------------------------------------------------------------------------- */
 double orc_adk_lnrate_general(double Ip_au, double Z, double F_au)
 {

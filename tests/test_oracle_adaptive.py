@@ -153,6 +153,22 @@ def test_early_stop_when_energy_constant(orc):
     assert early[3] < full[3]
 
 
+def test_energy_check_once_per_period(orc):
+    """Stop rule: the energy is compared at the first accepted step end at
+    least 0.999 optical period after the previous check (the first one after
+    birth).  In a uniform magnetic field gamma is constant, so a loose
+    tolerance stops the electron at its first check: between 0.999 T and
+    0.999 T + h_max after birth."""
+    L = orc.laser_intensity(0.8e-6, 3e-6, 30e-15, 1e21, field=orc.UNIFORM_EB,
+                            test_B=(0.0, 0.0, 500.0), window=1)
+    T = L.lambda_ / C
+    A = orc.adaptive(L=L, k_tol=1e-6)
+    t0 = -20e-15
+    xf, uf, ts, na, nr, st = orc.push_one_adaptive(L, A, t0, 100e-15, np.zeros(3),
+                                                   np.array([3.0, 0.0, 1.0]))
+    assert st == 0 and 0.999 * T <= ts - t0 <= 0.999 * T + A.h_max * (1 + 1e-12), (ts - t0) / T
+
+
 def test_step_budget_and_window_edges(orc):
     L = orc.laser_intensity(0.8e-6, 3e-6, 30e-15, 1e21)
     A = orc.adaptive(L=L, max_steps=5)

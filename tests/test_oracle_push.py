@@ -184,6 +184,11 @@ def test_batch_push_window_and_unborn(orc):
     tb = np.array([-30e-15 - 5e-6 / C, np.inf, np.inf, 10e-15 + 8e-6 / C])
     out = orc.push(L, tb, x0, y0, z0, 2)
     assert np.all(np.isnan([o[1] for o in out])) and np.all(np.isnan([o[2] for o in out]))
+    # births before the window: invalid (NaN) beyond one step ahead of the
+    # window start, valid within it (reading of the window convention)
+    ts0 = z0[0] / C - L.t_before
+    early = orc.push(L, np.array([ts0 - 1.5 * L.dt, ts0 - 0.5 * L.dt]), x0[:1], y0[:1], z0[:1], 2)
+    assert np.all(np.isnan([o[0] for o in early])) and np.all(np.isfinite([o[1] for o in early]))
     for s, a in ((0, 0), (3, 1)):
         te = z0[a] / C + L.t_after
         xf, uf = orc.push_one(L, tb[s], te, L.dt, [x0[a], y0[a], z0[a]], [0, 0, 0])
