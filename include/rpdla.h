@@ -201,6 +201,26 @@ rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots
                         double* uz, double* xf, double* yf, double* zf, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Allocation-free push, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, validation, kernels and results as rpdla_push;
+ * it calls no hipMalloc / hipFree and no allocating library routine.  Its
+ * work-queue counter lives in a 256-byte library-owned device array (one per
+ * GPU, held until the process ends, its address looked up on the first call
+ * on each device), cleared by a fill kernel at the start of every call.
+ * Limit: n_slots <= 2^40 (RPDLA_ERANGE beyond).  Every call on one GPU uses
+ * that GPU's array, so calls that overlap in time on one GPU (different
+ * streams, or several host threads) race on the counter and give wrong
+ * results: serialize them.  RPDLA_EHIP if the array's address cannot be
+ * obtained.
+ * ------------------------------------------------------------------------ */
+rpdla_status rpdla_push_noalloc(const rpdla_laser* L, int32_t precision, int64_t n_slots,
+                                const double* t_birth, const double* x0, const double* y0,
+                                const double* z0, int32_t slots_per_atom, double* ux,
+                                double* uy, double* uz, double* xf, double* yf, double* zf,
+                                void* stream);
+
+/* ------------------------------------------------------------------------
  * Push with the radiation term of Eq. (3) and the quantum parameter of
  * Eqs. (4)-(6) (Sec. 2.1).  Same slots, window, RK4 steps and outputs as
  * rpdla_push in RPDLA_FP64, with

@@ -94,6 +94,8 @@ def _load():
         "rpdla_batched_workspace_layout": (i32, [i32, i64, i32, i32, C.POINTER(C.c_size_t)]),
         "rpdla_histogram2d": (i32, [i64, vp, vp, vp, C.POINTER(rpdla_hist2d_spec), vp, vp, vp]),
         "rpdla_push": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "rpdla_push_noalloc": (i32, [LP, i32, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                                     vp]),
         "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
         "rpdla_epilogue": (i32, [i64, vp, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_batched_workspace_bytes": (C.c_size_t, [i32, i64, i32, i32]),
@@ -243,6 +245,21 @@ def rpdla_push(L, precision, t_birth, x0, y0, z0, slots_per_atom, out=None, stre
                           slots_per_atom, _dev(ux, "ux", n), _dev(uy, "uy", n), _dev(uz, "uz", n),
                           _dev(xf, "xf", n), _dev(yf, "yf", n), _dev(zf, "zf", n),
                           _stream(stream)), "rpdla_push")
+    return out
+
+
+def rpdla_push_noalloc(L, precision, t_birth, x0, y0, z0, slots_per_atom, out, stream=None):
+    """rpdla_push without device allocation: the caller passes the six output
+    tensors ``out`` = (ux, uy, uz, xf, yf, zf); the library's own 256-byte
+    device array holds the work counter (overlapping calls on one GPU race)."""
+    n = t_birth.numel()
+    na = (n + slots_per_atom - 1) // slots_per_atom
+    ux, uy, uz, xf, yf, zf = out
+    _check(lib.rpdla_push_noalloc(C.byref(L), precision, n, _dev(t_birth, "t_birth", n),
+                                  _dev(x0, "x0", na), _dev(y0, "y0", na), _dev(z0, "z0", na),
+                                  slots_per_atom, _dev(ux, "ux", n), _dev(uy, "uy", n),
+                                  _dev(uz, "uz", n), _dev(xf, "xf", n), _dev(yf, "yf", n),
+                                  _dev(zf, "zf", n), _stream(stream)), "rpdla_push_noalloc")
     return out
 
 

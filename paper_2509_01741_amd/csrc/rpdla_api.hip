@@ -19,6 +19,12 @@
 #include "rpdla_kernels.hpp"
 #include "rpdla_batched.hpp"
 
+// Scratch of the allocation-free push (rpdla_push_noalloc): word 0 is its
+// work-queue counter; the rest pads the array to 256 bytes.  Each GPU holds
+// its own copy until the process ends.
+constexpr int kScratchWords = 32;
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+
 namespace {
 
 using rpdla::DevCfg;
@@ -43,6 +49,9 @@ constexpr double kLnwSkip = -80.0;
 // Neon ionization potentials Ne^(k-1)+ -> Ne^k+ [eV] (NIST ASD).
 constexpr double kNeIpEv[10] = {21.564540, 40.96297, 63.4233, 97.1900, 126.247,
                                 157.934,   207.271,  239.0970, 1195.80784, 1362.19911};
+
+// Largest slot count of one push call.
+constexpr int64_t kMaxPushSlots = (int64_t)1 << 40;
 
 thread_local std::string g_err;
 
@@ -266,6 +275,71 @@ rpdla_status launch_push_dp(const DevCfg& c, const rpdla::PushIO& io, hipStream_
     return RPDLA_OK;
 }
 
+// Checks shared by rpdla_push and rpdla_push_noalloc (nothing is enqueued).
+rpdla_status check_push_args(const rpdla_laser* L, int32_t precision, int64_t n_slots,
+                             const double* t_birth, const double* x0, const double* y0,
+                             const double* z0, int32_t slots_per_atom, double* ux, double* uy,
+                             double* uz, double* xf, double* yf, double* zf)
+{
+    rpdla_status st = check_laser(L);
+    if (st != RPDLA_OK) return st;
+    if (!(precision == RPDLA_FP64 || precision == RPDLA_MIXED))
+        return fail(RPDLA_EINVAL, "unknown precision %d", precision);
+    if (n_slots < 0) return fail(RPDLA_EINVAL, "n_slots < 0");
+    if (slots_per_atom < 1) return fail(RPDLA_EINVAL, "slots_per_atom < 1");
+    if (n_slots == 0) return RPDLA_OK;
+    if (!t_birth || !x0 || !y0 || !z0 || !ux || !uy || !uz || !xf || !yf || !zf)
+        return fail(RPDLA_EINVAL, "null pointer");
+    if (n_slots > kMaxPushSlots) return fail(RPDLA_ERANGE, "n_slots too large");
+    return RPDLA_OK;
+}
+
+// Clear the work counter q (a fill kernel, no memset node) and launch the
+// persistent push that draws slots from it.
+rpdla_status enqueue_push(const rpdla_laser* L, int32_t precision, int64_t n_slots,
+                          const double* t_birth, const double* x0, const double* y0,
+                          const double* z0, int32_t slots_per_atom, double* ux, double* uy,
+                          double* uz, double* xf, double* yf, double* zf, unsigned long long* q,
+                          hipStream_t s)
+{
+    const DevCfg c = make_cfg(L);
+    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(64), 0, s, q, (int64_t)1);
+    RPDLA_HIP(hipGetLastError());
+    rpdla::PushIO io{t_birth, x0, y0, z0, slots_per_atom, n_slots, ux, uy, uz, xf, yf, zf, q};
+    switch (L->field) {
+    case 1: return launch_push<1>(c, precision, io, s);
+    case 3: return launch_push<3>(c, precision, io, s);
+    case 5: return launch_push<5>(c, precision, io, s);
+    case 10: return launch_push<10>(c, precision, io, s);
+    default: return launch_push<11>(c, precision, io, s);
+    }
+}
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (with that device current) and kept for the process lifetime.  The
+// array's name is only a host-side stand-in: kernels and copies get this
+// address.
+std::mutex g_scratch_mu;
+std::vector<unsigned long long*> g_scratch_ptr;
+
+rpdla_status scratch_address(unsigned long long** out)
+{
+    int dev = 0;
+    RPDLA_HIP(hipGetDevice(&dev));
+    if (dev < 0) return fail(RPDLA_EHIP, "hipGetDevice returned %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[(size_t)dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RPDLA_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[(size_t)dev] = (unsigned long long*)p;
+    }
+    *out = g_scratch_ptr[(size_t)dev];
+    return RPDLA_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -399,33 +473,33 @@ rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots
                         int32_t slots_per_atom, double* ux, double* uy, double* uz, double* xf,
                         double* yf, double* zf, void* stream)
 {
-    rpdla_status st = check_laser(L);
-    if (st != RPDLA_OK) return st;
-    if (!(precision == RPDLA_FP64 || precision == RPDLA_MIXED))
-        return fail(RPDLA_EINVAL, "unknown precision %d", precision);
-    if (n_slots < 0) return fail(RPDLA_EINVAL, "n_slots < 0");
-    if (slots_per_atom < 1) return fail(RPDLA_EINVAL, "slots_per_atom < 1");
-    if (n_slots == 0) return RPDLA_OK;
-    if (!t_birth || !x0 || !y0 || !z0 || !ux || !uy || !uz || !xf || !yf || !zf)
-        return fail(RPDLA_EINVAL, "null pointer");
-    if (n_slots > ((int64_t)1 << 40)) return fail(RPDLA_ERANGE, "n_slots too large");
-    const DevCfg c = make_cfg(L);
+    rpdla_status st = check_push_args(L, precision, n_slots, t_birth, x0, y0, z0, slots_per_atom,
+                                      ux, uy, uz, xf, yf, zf);
+    if (st != RPDLA_OK || n_slots == 0) return st;
     hipStream_t s = (hipStream_t)stream;
     unsigned long long* q = nullptr;
     RPDLA_HIP(hipMallocAsync((void**)&q, sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(64), 0, s, q, (int64_t)1);
-    rpdla::PushIO io{t_birth, x0, y0, z0, slots_per_atom, n_slots, ux, uy, uz, xf, yf, zf, q};
-    switch (L->field) {
-    case 1: st = launch_push<1>(c, precision, io, s); break;
-    case 3: st = launch_push<3>(c, precision, io, s); break;
-    case 5: st = launch_push<5>(c, precision, io, s); break;
-    case 10: st = launch_push<10>(c, precision, io, s); break;
-    default: st = launch_push<11>(c, precision, io, s); break;
-    }
+    st = enqueue_push(L, precision, n_slots, t_birth, x0, y0, z0, slots_per_atom, ux, uy, uz, xf,
+                      yf, zf, q, s);
     hipError_t fe = hipFreeAsync(q, s);
     if (st != RPDLA_OK) return st;
     if (fe != hipSuccess) return fail(RPDLA_EHIP, "hipFreeAsync: %s", hipGetErrorString(fe));
     return RPDLA_OK;
+}
+
+rpdla_status rpdla_push_noalloc(const rpdla_laser* L, int32_t precision, int64_t n_slots,
+                                const double* t_birth, const double* x0, const double* y0,
+                                const double* z0, int32_t slots_per_atom, double* ux, double* uy,
+                                double* uz, double* xf, double* yf, double* zf, void* stream)
+{
+    rpdla_status st = check_push_args(L, precision, n_slots, t_birth, x0, y0, z0, slots_per_atom,
+                                      ux, uy, uz, xf, yf, zf);
+    if (st != RPDLA_OK || n_slots == 0) return st;
+    unsigned long long* q = nullptr;
+    st = scratch_address(&q);
+    if (st != RPDLA_OK) return st;
+    return enqueue_push(L, precision, n_slots, t_birth, x0, y0, z0, slots_per_atom, ux, uy, uz,
+                        xf, yf, zf, q, (hipStream_t)stream);
 }
 
 rpdla_status rpdla_push_rr(const rpdla_laser* L, int32_t radiation_reaction, int64_t n_slots,
