@@ -22,6 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rpdla_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
+_LIB_EXT = os.path.join(_HERE, "liborc_ext.so")
 
 RP_O1, RP_O3, RP_O5, PLANE_LP, UNIFORM_EB = 1, 3, 5, 10, 11
 WIN_ARRIVAL, WIN_LAB = 0, 1
@@ -29,13 +30,16 @@ ANG_POLAR, ANG_AZIMUTH = 0, 1
 
 
 def build(force: bool = True) -> str:
-    """Compile ``rpdla_oracle.c`` into ``liborc.so`` (gcc -O2, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+    """Compile ``rpdla_oracle.c`` into ``liborc.so`` (gcc -O2, OpenMP) and,
+    with -DORC_EXTENDED, into ``liborc_ext.so`` (the same steps in x87
+    extended precision)."""
+    for path, extra in ((_LIB, []), (_LIB_EXT, ["-DORC_EXTENDED"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            tmp = path + ".tmp%d" % os.getpid()
+            cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall"] + extra + \
+                  ["-o", tmp, _SRC, "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(tmp, path)
     return _LIB
 
 
@@ -64,17 +68,34 @@ _I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 
 
 def lib():
+    """The oracle library (plain double), or the one RPDLA_ORACLE_LIB names:
+    the mutation check (tests/test_pins_mutations.py) points it at a copy with
+    one planted mistake, and the pins are also run against liborc_ext.so."""
     global _lib
-    if _lib is not None:
-        return _lib
-    path = os.environ.get("RPDLA_ORACLE_LIB")
-    if path is None:
-        # the mutation check (tests/test_pins_mutations.py) points this at a
-        # copy of the oracle with one planted mistake
-        path = _LIB
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if _lib is None:
+        path = os.environ.get("RPDLA_ORACLE_LIB")
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        _lib = _bind(C.CDLL(path))
+    return _lib
+
+
+_lib_ext = None
+
+
+def lib_extended():
+    """The same oracle built to compute in x87 extended precision."""
+    global _lib_ext
+    if _lib_ext is None:
+        if not os.path.exists(_LIB_EXT) or os.path.getmtime(_LIB_EXT) < os.path.getmtime(_SRC):
             build(force=True)
-    L = C.CDLL(path)
+        _lib_ext = _bind(C.CDLL(_LIB_EXT))
+    return _lib_ext
+
+
+def _bind(L):
     LP = C.POINTER(Laser)
     sig = {
         "orc_constants": (None, [_D]),
@@ -115,13 +136,15 @@ def lib():
         "orc_push_adaptive": (None, [LP, C.POINTER(Adaptive), C.c_int64, _D, _D, _D, _D, C.c_int,
                                      _D, _D, _D, _D, _D, _D, _D, _I64, _I64]),
         "orc_dp_tableau": (None, [_D, _D, _D, _D]),
-        "orc_ne_ip_table": (C.POINTER(C.c_double), []),
+        "orc_ne_ip_table": (None, [_D]),
+        "orc_is_extended": (C.c_int, []),
+        "orc_chain": (None, [LP, C.c_uint64, C.c_uint32, _U64, C.c_int64, C.c_double,
+                             C.c_double, C.c_int, C.c_int, _D, _D, _D, _D, _D, _D, _D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = L
     return L
 
 
@@ -137,8 +160,9 @@ def constants() -> dict:
 
 
 def ne_ip_ev() -> np.ndarray:
-    p = lib().orc_ne_ip_table()
-    return np.array([p[i] for i in range(10)])
+    out = np.zeros(10)
+    lib().orc_ne_ip_table(out)
+    return out
 
 
 def laser_intensity(lam, w0, tau_fwhm, I_W_cm2, **kw) -> Laser:
@@ -363,3 +387,24 @@ def push_adaptive(L: Laser, A: Adaptive, t_birth, x0, y0, z0, slots_per_atom):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def is_extended(extended=False) -> bool:
+    return bool((lib_extended() if extended else lib()).orc_is_extended())
+
+
+def chain(L: Laser, seed, cfg, atoms, r_max, z_half, k_first, k_last, extended=False):
+    """Sampling, ionization, push and kinetic energy of the atoms with the
+    given indices in one pass, nothing rounded to double between the steps;
+    extended=True runs it in x87 extended precision.  Returns dict x, y, z [n]
+    and t_birth, ux, uy, uz, K [n K] (slot j K + s: atom atoms[j], state
+    k_first + s)."""
+    atoms = np.ascontiguousarray(atoms, dtype=np.uint64).ravel()
+    n = atoms.size
+    K = k_last - k_first + 1
+    out = {k: np.zeros(n) for k in ("x", "y", "z")}
+    out.update({k: np.zeros(n * K) for k in ("t_birth", "ux", "uy", "uz", "K")})
+    (lib_extended() if extended else lib()).orc_chain(
+        C.byref(L), seed, cfg, atoms, n, r_max, z_half, k_first, k_last, out["x"], out["y"],
+        out["z"], out["t_birth"], out["ux"], out["uy"], out["uz"], out["K"])
+    return out

@@ -37,31 +37,53 @@
  * the state -> (potential, charge) mapping through the hydrogen-like last
  * neon electron, and the power of the field at every neon n*.
  */
-#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <tgmath.h>
+#undef I   /* the imaginary unit of <complex.h>; nothing here is complex */
+
+/* Working precision.  The oracle is plain double; the same source built with
+ * -DORC_EXTENDED computes every step in x87 extended precision (64-bit
+ * significand, 2^11 finer than double) with the same arguments and outputs,
+ * as the reference that tells which double results are determined to a
+ * given tolerance at all.  <tgmath.h> picks each math function's precision
+ * from its argument; ORC_R marks a decimal constant of working precision. */
+#ifdef ORC_EXTENDED
+typedef long double orc_real;
+#define ORC_R(x) x##L
+#else
+typedef double orc_real;
+#define ORC_R(x) x
+#endif
+
+/* The crossing solve stops at a Newton correction of at most
+ * 2^ORC_CROSS_TOL_EXP max(|t|, T) (the last correction is applied, so the
+ * result is accurate to about the square of that). */
+#ifndef ORC_CROSS_TOL_EXP
+#define ORC_CROSS_TOL_EXP (-40)
+#endif
 
 /* ---------------------------------------------------------------------------
  * Constants (CODATA 2018 exact / recommended values, SI).
  * ------------------------------------------------------------------------- */
-#define ORC_C        299792458.0            /* speed of light, m/s            */
-#define ORC_QE       1.602176634e-19        /* elementary charge, C           */
-#define ORC_ME       9.1093837015e-31       /* electron mass, kg              */
-#define ORC_EPS0     8.8541878128e-12       /* vacuum permittivity, F/m       */
-#define ORC_MEC2_MEV 0.51099895000          /* electron rest energy, MeV      */
-#define ORC_EA       5.14220674763e11       /* atomic unit of field, V/m      */
-#define ORC_TAUA     2.4188843265857e-17    /* atomic unit of time, s         */
-#define ORC_EH_EV    27.211386245988        /* Hartree energy, eV             */
-#define ORC_PI       3.14159265358979323846
-#define ORC_HBAR     1.054571817e-34        /* reduced Planck constant, J s   */
-#define ORC_ALPHA    7.2973525693e-3        /* fine-structure constant        */
+#define ORC_C        ORC_R(299792458.0)         /* speed of light, m/s        */
+#define ORC_QE       ORC_R(1.602176634e-19)     /* elementary charge, C       */
+#define ORC_ME       ORC_R(9.1093837015e-31)    /* electron mass, kg          */
+#define ORC_EPS0     ORC_R(8.8541878128e-12)    /* vacuum permittivity, F/m   */
+#define ORC_MEC2_MEV ORC_R(0.51099895000)       /* electron rest energy, MeV  */
+#define ORC_EA       ORC_R(5.14220674763e11)    /* atomic unit of field, V/m  */
+#define ORC_TAUA     ORC_R(2.4188843265857e-17) /* atomic unit of time, s     */
+#define ORC_EH_EV    ORC_R(27.211386245988)     /* Hartree energy, eV         */
+#define ORC_PI       ORC_R(3.14159265358979323846264338327950288)
+#define ORC_HBAR     ORC_R(1.054571817e-34)     /* reduced Planck constant, J s */
+#define ORC_ALPHA    ORC_R(7.2973525693e-3)     /* fine-structure constant    */
 
 /* Neon ionization potentials Ne^(k-1)+ -> Ne^k+, k = 1..10, in eV (NIST ASD
  * values; the paper names the charge states but prints no potentials). */
-static const double orc_ne_ip_ev[10] = {
-    21.564540, 40.96297, 63.4233, 97.1900, 126.247,
-    157.934, 207.271, 239.0970, 1195.80784, 1362.19911};
+static const orc_real orc_ne_ip_ev[10] = {
+    ORC_R(21.564540), ORC_R(40.96297), ORC_R(63.4233), ORC_R(97.1900), ORC_R(126.247),
+    ORC_R(157.934), ORC_R(207.271), ORC_R(239.0970), ORC_R(1195.80784), ORC_R(1362.19911)};
 
 /* field models */
 enum { ORC_RP_O1 = 1, ORC_RP_O3 = 3, ORC_RP_O5 = 5,
@@ -88,7 +110,20 @@ typedef struct {
     int angle;
 } orc_hist_spec;
 
-const double* orc_ne_ip_table(void) { return orc_ne_ip_ev; }
+void orc_ne_ip_table(double out[10])
+{
+    for (int i = 0; i < 10; ++i) out[i] = (double)orc_ne_ip_ev[i];
+}
+
+/* 1 in the extended-precision build, 0 in the plain one. */
+int orc_is_extended(void)
+{
+#ifdef ORC_EXTENDED
+    return 1;
+#else
+    return 0;
+#endif
+}
 
 void orc_constants(double out[8])
 {
@@ -188,20 +223,29 @@ double orc_uniform(uint64_t seed, uint32_t cfg, uint64_t atom, int j)
 /* Focal-volume sampling (Sec. 2.1): ions at rest, uniform in a cylinder about
  * the propagation axis, focus at the origin: r = R sqrt(u0),
  * azimuth 2 pi u1, z = zh (2 u2 - 1). */
+static void orc_sample_one(uint64_t seed, uint32_t cfg, uint64_t a, orc_real r_max,
+                           orc_real z_half, orc_real* x, orc_real* y, orc_real* z)
+{
+    double u0 = orc_uniform(seed, cfg, a, 0);
+    double u1 = orc_uniform(seed, cfg, a, 1);
+    double u2 = orc_uniform(seed, cfg, a, 2);
+    orc_real r = r_max * sqrt((orc_real)u0);
+    orc_real th = 2.0 * ORC_PI * u1;
+    *x = r * cos(th);
+    *y = r * sin(th);
+    *z = z_half * (2.0 * u2 - 1.0);
+}
+
 void orc_sample_atoms(uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n,
                       double r_max, double z_half, double* x, double* y, double* z)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        uint64_t a = first_atom + (uint64_t)i;
-        double u0 = orc_uniform(seed, cfg, a, 0);
-        double u1 = orc_uniform(seed, cfg, a, 1);
-        double u2 = orc_uniform(seed, cfg, a, 2);
-        double r = r_max * sqrt(u0);
-        double th = 2.0 * ORC_PI * u1;
-        x[i] = r * cos(th);
-        y[i] = r * sin(th);
-        z[i] = z_half * (2.0 * u2 - 1.0);
+        orc_real xr, yr, zr;
+        orc_sample_one(seed, cfg, first_atom + (uint64_t)i, r_max, z_half, &xr, &yr, &zr);
+        x[i] = (double)xr;
+        y[i] = (double)yr;
+        z[i] = (double)zr;
     }
 }
 
@@ -239,45 +283,45 @@ void orc_sample_atoms(uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t 
  * Test models: a linearly polarized plane wave Ex = A env cos(omega t - k z
  * + phi0), By = Ex/c, and uniform static E and B.
  * ------------------------------------------------------------------------- */
-void orc_field(const orc_laser* L, double x, double y, double z, double t,
-               double E[3], double B[3])
+static void orc_field(const orc_laser* L, orc_real x, orc_real y, orc_real z, orc_real t,
+                      orc_real E[3], orc_real B[3])
 {
-    const double k = 2.0 * ORC_PI / L->lambda;
-    const double om = ORC_C * k;
-    const double tau0 = L->tau_fwhm / sqrt(2.0 * log(2.0));
+    const orc_real k = 2.0 * ORC_PI / L->lambda;
+    const orc_real om = ORC_C * k;
+    const orc_real tau0 = L->tau_fwhm / sqrt(2.0 * log((orc_real)2.0));
     if (L->field == ORC_UNIFORM_EB) {
         for (int i = 0; i < 3; ++i) { E[i] = L->test_E[i]; B[i] = L->test_B[i]; }
         return;
     }
     if (L->field == ORC_PLANE_LP) {
-        double s = (t - z / ORC_C) / tau0;
-        double ex = L->amp * exp(-s * s) * cos(om * t - k * z + L->phi0);
+        orc_real s = (t - z / ORC_C) / tau0;
+        orc_real ex = L->amp * exp(-s * s) * cos(om * t - k * z + L->phi0);
         E[0] = ex; E[1] = 0.0; E[2] = 0.0;
         B[0] = 0.0; B[1] = ex / ORC_C; B[2] = 0.0;
         return;
     }
     const int order = L->field;
-    const double w0 = L->w0;
-    const double zr = 0.5 * k * w0 * w0;
-    const double eps = w0 / zr;
-    const double rho2 = (x * x + y * y) / (w0 * w0);
-    const double zeta = z / zr;
-    const double D = 1.0 + zeta * zeta;
-    const double Psi = L->phi0 + om * t - k * z - rho2 * zeta / D;
-    const double s = (t - z / ORC_C) / tau0;
-    const double g = exp(-rho2 / D - s * s);
-    const double gouy = atan(zeta);
-    double C[9], S[9];
+    const orc_real w0 = L->w0;
+    const orc_real zr = 0.5 * k * w0 * w0;
+    const orc_real eps = w0 / zr;
+    const orc_real rho2 = (x * x + y * y) / (w0 * w0);
+    const orc_real zeta = z / zr;
+    const orc_real D = 1.0 + zeta * zeta;
+    const orc_real Psi = L->phi0 + om * t - k * z - rho2 * zeta / D;
+    const orc_real s = (t - z / ORC_C) / tau0;
+    const orc_real g = exp(-rho2 / D - s * s);
+    const orc_real gouy = atan(zeta);
+    orc_real C[9], S[9];
     for (int n = 2; n <= 8; ++n) {
-        double a = L->amp * g * pow(D, -0.5 * n);
+        orc_real a = L->amp * g * pow(D, -0.5 * n);
         C[n] = a * cos(Psi + n * gouy);
         S[n] = a * sin(Psi + n * gouy);
     }
-    const double r2 = rho2, r4 = rho2 * rho2, r6 = r4 * rho2, r8 = r4 * r4;
-    const double e2 = eps * eps, e3 = e2 * eps, e4 = e2 * e2;
-    double PE = C[2];
-    double PB = C[2];
-    double Ez = eps * (S[2] - r2 * S[3]);
+    const orc_real r2 = rho2, r4 = rho2 * rho2, r6 = r4 * rho2, r8 = r4 * r4;
+    const orc_real e2 = eps * eps, e3 = e2 * eps, e4 = e2 * e2;
+    orc_real PE = C[2];
+    orc_real PB = C[2];
+    orc_real Ez = eps * (S[2] - r2 * S[3]);
     if (order >= 3) {
         PE += e2 * (-C[3] / 2.0 + r2 * C[4] - r4 * C[5] / 4.0);
         PB += e2 * (C[3] / 2.0 + r2 * C[4] / 2.0 - r4 * C[5] / 4.0);
@@ -309,69 +353,84 @@ void orc_field(const orc_laser* L, double x, double y, double z, double t,
  * exactly zero when F = 0 or ln(w [1/s]) < -700.  Parity unpinned: the n*
  * dependence of C^2 (see the header of this file).
  * ------------------------------------------------------------------------- */
-double orc_adk_lnrate_general(double Ip_au, double Z, double F_au)
+static orc_real orc_adk_lnrate_r(orc_real Ip_au, orc_real Z, orc_real F_au)
 {
-    double nstar = Z / sqrt(2.0 * Ip_au);
-    double F0 = pow(2.0 * Ip_au, 1.5);
-    double lnC2 = 2.0 * nstar * log(2.0) - log(nstar) - lgamma(2.0 * nstar);
+    orc_real nstar = Z / sqrt(2.0 * Ip_au);
+    orc_real F0 = pow(2.0 * Ip_au, (orc_real)1.5);
+    orc_real lnC2 = 2.0 * nstar * log((orc_real)2.0) - log(nstar) - lgamma(2.0 * nstar);
     return lnC2 + log(Ip_au / ORC_TAUA) + (2.0 * nstar - 1.0) * log(2.0 * F0 / F_au)
            - 2.0 * F0 / (3.0 * F_au);
 }
 
-/* ln of the rate [1/s] of Ne^(k-1)+ -> Ne^k+ at field magnitude Emag [V/m]. */
-double orc_adk_lnrate(int k, double Emag)
+double orc_adk_lnrate_general(double Ip_au, double Z, double F_au)
 {
-    double Ip = orc_ne_ip_ev[k - 1] / ORC_EH_EV;
-    return orc_adk_lnrate_general(Ip, (double)k, Emag / ORC_EA);
+    return (double)orc_adk_lnrate_r(Ip_au, Z, F_au);
 }
 
-double orc_adk_rate(int k, double Emag)
+/* ln of the rate [1/s] of Ne^(k-1)+ -> Ne^k+ at field magnitude Emag [V/m]. */
+static orc_real orc_adk_lnrate_k(int k, orc_real Emag)
+{
+    orc_real Ip = orc_ne_ip_ev[k - 1] / ORC_EH_EV;
+    return orc_adk_lnrate_r(Ip, (orc_real)k, Emag / ORC_EA);
+}
+
+double orc_adk_lnrate(int k, double Emag) { return (double)orc_adk_lnrate_k(k, Emag); }
+
+static orc_real orc_adk_rate_k(int k, orc_real Emag)
 {
     if (!(Emag > 0.0)) return 0.0;
-    double l = orc_adk_lnrate(k, Emag);
+    orc_real l = orc_adk_lnrate_k(k, Emag);
     if (l < -700.0) return 0.0;
     return exp(l);
 }
 
-static double orc_emag(const orc_laser* L, double x, double y, double z, double t)
+double orc_adk_rate(int k, double Emag) { return (double)orc_adk_rate_k(k, Emag); }
+
+static orc_real orc_emag(const orc_laser* L, orc_real x, orc_real y, orc_real z, orc_real t)
 {
-    double E[3], B[3];
+    orc_real E[3], B[3];
     orc_field(L, x, y, z, t, E, B);
     return sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
 }
 
 /* 4-point Gauss-Legendre nodes / weights on [-1, 1], closed form. */
-static void orc_gl4(double xn[4], double wn[4])
+static void orc_gl4(orc_real xn[4], orc_real wn[4])
 {
-    double a = sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(6.0 / 5.0));
-    double b = sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(6.0 / 5.0));
-    double wa = (18.0 + sqrt(30.0)) / 36.0;
-    double wb = (18.0 - sqrt(30.0)) / 36.0;
+    const orc_real three = 3.0, two = 2.0, six = 6.0, thirty = 30.0;
+    orc_real a = sqrt(three / 7.0 - two / 7.0 * sqrt(six / 5.0));
+    orc_real b = sqrt(three / 7.0 + two / 7.0 * sqrt(six / 5.0));
+    orc_real wa = (18.0 + sqrt(thirty)) / 36.0;
+    orc_real wb = (18.0 - sqrt(thirty)) / 36.0;
     xn[0] = -b; xn[1] = -a; xn[2] = a; xn[3] = b;
     wn[0] = wb; wn[1] = wa; wn[2] = wa; wn[3] = wb;
 }
 
-void orc_gl4_table(double xn[4], double wn[4]) { orc_gl4(xn, wn); }
+void orc_gl4_table(double xn[4], double wn[4])
+{
+    orc_real x[4], w[4];
+    orc_gl4(x, w);
+    for (int i = 0; i < 4; ++i) { xn[i] = (double)x[i]; wn[i] = (double)w[i]; }
+}
 
 /* GL-4 estimate of the integral of w_k(|E(x,t)|) dt over [a, b]. */
-static double orc_rate_integral(const orc_laser* L, int k, double x, double y, double z,
-                                double a, double b)
+static orc_real orc_rate_integral(const orc_laser* L, int k, orc_real x, orc_real y, orc_real z,
+                                  orc_real a, orc_real b)
 {
-    double xn[4], wn[4];
+    orc_real xn[4], wn[4];
     orc_gl4(xn, wn);
-    double h = 0.5 * (b - a), m = 0.5 * (a + b);
-    double s = 0.0;
+    orc_real h = 0.5 * (b - a), m = 0.5 * (a + b);
+    orc_real s = 0.0;
     for (int i = 0; i < 4; ++i)
-        s += wn[i] * orc_adk_rate(k, orc_emag(L, x, y, z, m + h * xn[i]));
+        s += wn[i] * orc_adk_rate_k(k, orc_emag(L, x, y, z, m + h * xn[i]));
     return h * s;
 }
 
 /* Window of an atom at axial position z (reading: the bounds -5 tau, +10 tau
  * are taken relative to the pulse peak's arrival at the atom, z/c, so that
  * every atom sees the whole pulse; the lab-frame window is the alternative). */
-static void orc_window(const orc_laser* L, double z, double* ts, double* te)
+static void orc_window(const orc_laser* L, orc_real z, orc_real* ts, orc_real* te)
 {
-    double tz = (L->window == ORC_WIN_ARRIVAL) ? z / ORC_C : 0.0;
+    orc_real tz = (L->window == ORC_WIN_ARRIVAL) ? z / ORC_C : 0.0;
     *ts = tz - L->t_before;
     *te = tz + L->t_after;
 }
@@ -381,28 +440,29 @@ static void orc_window(const orc_laser* L, double z, double* ts, double* te)
  * the bracket by bisection.  Start from linear interpolation on the panel;
  * accept t - d as soon as a Newton correction d is at most
  * 2^-40 max(|t|, T), or stop when a bisection step is that small. */
-static double orc_solve_crossing(const orc_laser* L, int k, double x, double y, double z,
-                                 double lo, double hi, double target, double Ghi)
+static orc_real orc_solve_crossing(const orc_laser* L, int k, orc_real x, orc_real y,
+                                   orc_real z, orc_real lo, orc_real hi, orc_real target,
+                                   orc_real Ghi)
 {
     if (!(target > 0.0)) return lo;
-    const double T = L->lambda / ORC_C;
-    double tl = lo, th = hi;
-    double t = lo + (hi - lo) * (target / Ghi);
+    const orc_real T = L->lambda / ORC_C;
+    orc_real tl = lo, th = hi;
+    orc_real t = lo + (hi - lo) * (target / Ghi);
     if (!(t > tl && t < th)) t = 0.5 * (tl + th);
     for (int it = 0; it < 100; ++it) {
-        double gdiff = orc_rate_integral(L, k, x, y, z, lo, t) - target;
+        orc_real gdiff = orc_rate_integral(L, k, x, y, z, lo, t) - target;
         if (gdiff == 0.0) return t;
         if (gdiff > 0.0) th = t; else tl = t;
-        const double tol = ldexp(fmax(fabs(t), T), -40);
-        double w = orc_adk_rate(k, orc_emag(L, x, y, z, t));
-        double tn = NAN;
+        const orc_real tol = ldexp(fmax(fabs(t), T), ORC_CROSS_TOL_EXP);
+        orc_real w = orc_adk_rate_k(k, orc_emag(L, x, y, z, t));
+        orc_real tn = NAN;
         if (w > 0.0) {
-            double d = gdiff / w;
+            orc_real d = gdiff / w;
             if (fabs(d) <= tol) return t - d;   /* converged Newton step */
             tn = t - d;
         }
         if (!(tn > tl && tn < th)) tn = 0.5 * (tl + th);
-        double step = fabs(tn - t);
+        orc_real step = fabs(tn - t);
         t = tn;
         if (step <= tol) break;                 /* bracket below tolerance */
     }
@@ -416,36 +476,45 @@ static double orc_solve_crossing(const orc_laser* L, int k, double x, double y, 
  * Integrals use GL-4 on panels of width dt laid from the window start; a
  * state that starts inside a panel integrates the remainder of that panel.
  * +INF marks a state not reached inside the window (and every later state). */
-void orc_ionize_one(const orc_laser* L, uint64_t seed, uint32_t cfg, uint64_t atom,
-                    double x, double y, double z, int k_first, int k_last, double* tb)
+static void orc_ionize_atom(const orc_laser* L, uint64_t seed, uint32_t cfg, uint64_t atom,
+                            orc_real x, orc_real y, orc_real z, int k_first, int k_last,
+                            orc_real* tb)
 {
     const int K = k_last - k_first + 1;
     for (int s = 0; s < K; ++s) tb[s] = INFINITY;
-    double ts, te;
+    orc_real ts, te;
     orc_window(L, z, &ts, &te);
-    const double h = L->dt;
+    const orc_real h = L->dt;
     const int64_t M = (int64_t)ceil((te - ts) / h);
     int s = 0;
-    double target = -log(orc_uniform(seed, cfg, atom, k_first + 2));
-    double I = 0.0;
-    double tstart = ts;
+    orc_real target = -log((orc_real)orc_uniform(seed, cfg, atom, k_first + 2));
+    orc_real I = 0.0;
+    orc_real tstart = ts;
     for (int64_t j = 0; j < M && s < K; ++j) {
-        double a = ts + (double)j * h;
-        double b = (j == M - 1) ? te : ts + (double)(j + 1) * h;
+        orc_real a = ts + (orc_real)j * h;
+        orc_real b = (j == M - 1) ? te : ts + (orc_real)(j + 1) * h;
         while (s < K) {
-            double lo = (tstart > a) ? tstart : a;
-            double seg = orc_rate_integral(L, k_first + s, x, y, z, lo, b);
+            orc_real lo = (tstart > a) ? tstart : a;
+            orc_real seg = orc_rate_integral(L, k_first + s, x, y, z, lo, b);
             if (I + seg < target) { I += seg; break; }
-            double t = orc_solve_crossing(L, k_first + s, x, y, z, lo, b, target - I, seg);
+            orc_real t = orc_solve_crossing(L, k_first + s, x, y, z, lo, b, target - I, seg);
             tb[s] = t;
             ++s;
             if (s < K) {
-                target = -log(orc_uniform(seed, cfg, atom, k_first + s + 2));
+                target = -log((orc_real)orc_uniform(seed, cfg, atom, k_first + s + 2));
                 I = 0.0;
                 tstart = t;
             }
         }
     }
+}
+
+void orc_ionize_one(const orc_laser* L, uint64_t seed, uint32_t cfg, uint64_t atom,
+                    double x, double y, double z, int k_first, int k_last, double* tb)
+{
+    orc_real t[10];
+    orc_ionize_atom(L, seed, cfg, atom, x, y, z, k_first, k_last, t);
+    for (int s = 0; s < k_last - k_first + 1; ++s) tb[s] = (double)t[s];
 }
 
 void orc_ionize(const orc_laser* L, uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n,
@@ -469,28 +538,29 @@ void orc_ionize(const orc_laser* L, uint64_t seed, uint32_t cfg, uint64_t first_
  * makes the discretized result unique).  Step n starts at t0 + n h; the
  * last step ends exactly at t_end.
  * ------------------------------------------------------------------------- */
-static void orc_rhs(const orc_laser* L, double t, const double Y[6], double dY[6])
+static void orc_rhs(const orc_laser* L, orc_real t, const orc_real Y[6], orc_real dY[6])
 {
-    double E[3], B[3];
+    orc_real E[3], B[3];
     orc_field(L, Y[0], Y[1], Y[2], t, E, B);
-    double gam = sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
-    double vx = ORC_C * Y[3] / gam, vy = ORC_C * Y[4] / gam, vz = ORC_C * Y[5] / gam;
-    const double q = -ORC_QE / (ORC_ME * ORC_C);
+    orc_real gam = sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
+    orc_real vx = ORC_C * Y[3] / gam, vy = ORC_C * Y[4] / gam, vz = ORC_C * Y[5] / gam;
+    const orc_real q = -ORC_QE / (ORC_ME * ORC_C);
     dY[0] = vx; dY[1] = vy; dY[2] = vz;
     dY[3] = q * (E[0] + (vy * B[2] - vz * B[1]));
     dY[4] = q * (E[1] + (vz * B[0] - vx * B[2]));
     dY[5] = q * (E[2] + (vx * B[1] - vy * B[0]));
 }
 
-void orc_push_one(const orc_laser* L, double t0, double t_end, double h,
-                  const double x0[3], const double u0[3], double xf[3], double uf[3])
+static void orc_push_elec(const orc_laser* L, orc_real t0, orc_real t_end, orc_real h,
+                          const orc_real x0[3], const orc_real u0[3], orc_real xf[3],
+                          orc_real uf[3])
 {
-    double Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
+    orc_real Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
     const int64_t N = (int64_t)ceil((t_end - t0) / h);
     for (int64_t n = 0; n < N; ++n) {
-        double ta = t0 + (double)n * h;
-        double hn = (n == N - 1) ? t_end - ta : h;
-        double k1[6], k2[6], k3[6], k4[6], Yt[6];
+        orc_real ta = t0 + (orc_real)n * h;
+        orc_real hn = (n == N - 1) ? t_end - ta : h;
+        orc_real k1[6], k2[6], k3[6], k4[6], Yt[6];
         orc_rhs(L, ta, Y, k1);
         for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];
         orc_rhs(L, ta + 0.5 * hn, Yt, k2);
@@ -502,6 +572,14 @@ void orc_push_one(const orc_laser* L, double t0, double t_end, double h,
             Y[i] += hn / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
     }
     for (int i = 0; i < 3; ++i) { xf[i] = Y[i]; uf[i] = Y[3 + i]; }
+}
+
+void orc_push_one(const orc_laser* L, double t0, double t_end, double h,
+                  const double x0[3], const double u0[3], double xf[3], double uf[3])
+{
+    orc_real X0[3] = {x0[0], x0[1], x0[2]}, U0[3] = {u0[0], u0[1], u0[2]}, XF[3], UF[3];
+    orc_push_elec(L, t0, t_end, h, X0, U0, XF, UF);
+    for (int i = 0; i < 3; ++i) { xf[i] = (double)XF[i]; uf[i] = (double)UF[i]; }
 }
 
 /* Push every born slot from rest (Sec. 2.1: electrons born with zero
@@ -520,16 +598,59 @@ void orc_push(const orc_laser* L, int64_t n_slots, const double* t_birth,
             ux[s] = uy[s] = uz[s] = xf[s] = yf[s] = zf[s] = NAN;
             continue;
         }
-        double ts, te;
+        orc_real ts, te;
         orc_window(L, z0[a], &ts, &te);
         if (!(t0 >= ts - L->dt)) {   /* birth before the window: invalid slot */
             ux[s] = uy[s] = uz[s] = xf[s] = yf[s] = zf[s] = NAN;
             continue;
         }
-        double X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
-        orc_push_one(L, t0, te, L->dt, X0, U0, XF, UF);
-        ux[s] = UF[0]; uy[s] = UF[1]; uz[s] = UF[2];
-        xf[s] = XF[0]; yf[s] = XF[1]; zf[s] = XF[2];
+        orc_real X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
+        orc_push_elec(L, t0, te, L->dt, X0, U0, XF, UF);
+        ux[s] = (double)UF[0]; uy[s] = (double)UF[1]; uz[s] = (double)UF[2];
+        xf[s] = (double)XF[0]; yf[s] = (double)XF[1]; zf[s] = (double)XF[2];
+    }
+}
+
+/* Kinetic energy m c^2 u^2 / (gamma + 1) [MeV] of normalized momentum u. */
+static orc_real orc_kinetic(const orc_real u[3])
+{
+    orc_real u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return ORC_MEC2_MEV * u2 / (sqrt(1.0 + u2) + 1.0);
+}
+
+/* The whole chain for the atoms with indices atoms[0..n-1], in working
+ * precision, with nothing rounded to double between the steps: sampling in a
+ * cylinder r < r_max, |z| < z_half, ionization times of states
+ * k_first..k_last, the push of every born electron from its birth and its
+ * kinetic energy.  Outputs are rounded to double at the end: positions
+ * x, y, z [n]; per slot t_birth, ux, uy, uz, K_MeV [n K] (+INF / NaN as for
+ * orc_ionize / orc_push).  In the plain build this equals orc_sample_atoms,
+ * orc_ionize, orc_push and orc_epilogue called in turn. */
+void orc_chain(const orc_laser* L, uint64_t seed, uint32_t cfg, const uint64_t* atoms, int64_t n,
+               double r_max, double z_half, int k_first, int k_last, double* x, double* y,
+               double* z, double* t_birth, double* ux, double* uy, double* uz, double* K_MeV)
+{
+    const int K = k_last - k_first + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n; ++i) {
+        orc_real X[3], tb[10];
+        orc_sample_one(seed, cfg, atoms[i], r_max, z_half, &X[0], &X[1], &X[2]);
+        x[i] = (double)X[0]; y[i] = (double)X[1]; z[i] = (double)X[2];
+        orc_ionize_atom(L, seed, cfg, atoms[i], X[0], X[1], X[2], k_first, k_last, tb);
+        orc_real ts, te;
+        orc_window(L, X[2], &ts, &te);
+        for (int k = 0; k < K; ++k) {
+            const int64_t sl = i * K + k;
+            t_birth[sl] = (double)tb[k];
+            if (!(tb[k] < INFINITY) || !(tb[k] >= ts - L->dt)) {
+                ux[sl] = uy[sl] = uz[sl] = K_MeV[sl] = NAN;
+                continue;
+            }
+            orc_real U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
+            orc_push_elec(L, tb[k], te, L->dt, X, U0, XF, UF);
+            ux[sl] = (double)UF[0]; uy[sl] = (double)UF[1]; uz[sl] = (double)UF[2];
+            K_MeV[sl] = (double)orc_kinetic(UF);
+        }
     }
 }
 
@@ -596,7 +717,11 @@ void orc_histogram(int64_t n, const double* t_birth, const double* ux, const dou
 void orc_field_batch(const orc_laser* L, int64_t n, const double* x, const double* y,
                      const double* z, const double* t, double* E, double* B)
 {
-    for (int64_t i = 0; i < n; ++i) orc_field(L, x[i], y[i], z[i], t[i], E + 3 * i, B + 3 * i);
+    for (int64_t i = 0; i < n; ++i) {
+        orc_real e[3], b[3];
+        orc_field(L, x[i], y[i], z[i], t[i], e, b);
+        for (int j = 0; j < 3; ++j) { E[3 * i + j] = (double)e[j]; B[3 * i + j] = (double)b[j]; }
+    }
 }
 
 void orc_uniform_batch(uint64_t seed, uint32_t cfg, int64_t n, const uint64_t* atom,
@@ -722,52 +847,64 @@ void orc_histogram2d(int64_t n, const double* a, const double* b, const double* 
  * (rr = 1) or off (rr = 0) and records, per electron, the largest chi met at
  * the start of its RK4 steps (0 if it takes none).
  * ------------------------------------------------------------------------- */
-double orc_critical_field(void)
+static orc_real orc_ecr(void)
 {
     return ORC_ME * ORC_ME * ORC_C * ORC_C * ORC_C / (ORC_QE * ORC_HBAR);
 }
 
+double orc_critical_field(void) { return (double)orc_ecr(); }
+
 /* du/dt of Eq. (3)'s radiation term (u = p / m c) and chi, for state Y at t. */
-void orc_rr_terms(const orc_laser* L, double t, const double Y[6], double duRR[3], double* chi)
+static void orc_rr_terms_r(const orc_laser* L, orc_real t, const orc_real Y[6], orc_real duRR[3],
+                           orc_real* chi)
 {
-    double E[3], B[3];
+    orc_real E[3], B[3];
     orc_field(L, Y[0], Y[1], Y[2], t, E, B);
-    const double gam = sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
-    const double v[3] = {ORC_C * Y[3] / gam, ORC_C * Y[4] / gam, ORC_C * Y[5] / gam};
-    const double f[3] = {E[0] + (v[1] * B[2] - v[2] * B[1]),
-                         E[1] + (v[2] * B[0] - v[0] * B[2]),
-                         E[2] + (v[0] * B[1] - v[1] * B[0])};
-    const double vE = (v[0] * E[0] + v[1] * E[1] + v[2] * E[2]) / ORC_C;
-    double Q = f[0] * f[0] + f[1] * f[1] + f[2] * f[2] - vE * vE;
+    const orc_real gam = sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
+    const orc_real v[3] = {ORC_C * Y[3] / gam, ORC_C * Y[4] / gam, ORC_C * Y[5] / gam};
+    const orc_real f[3] = {E[0] + (v[1] * B[2] - v[2] * B[1]),
+                           E[1] + (v[2] * B[0] - v[0] * B[2]),
+                           E[2] + (v[0] * B[1] - v[1] * B[0])};
+    const orc_real vE = (v[0] * E[0] + v[1] * E[1] + v[2] * E[2]) / ORC_C;
+    orc_real Q = f[0] * f[0] + f[1] * f[1] + f[2] * f[2] - vE * vE;
     if (Q < 0.0) Q = 0.0;
-    const double e2 = ORC_QE * ORC_QE;
-    const double coef = e2 * e2 * gam * gam /
-                        (6.0 * ORC_PI * ORC_EPS0 * ORC_ME * ORC_ME * ORC_C * ORC_C * ORC_C * ORC_C * ORC_C);
+    const orc_real e2 = ORC_QE * ORC_QE;
+    const orc_real coef = e2 * e2 * gam * gam /
+                          (6.0 * ORC_PI * ORC_EPS0 * ORC_ME * ORC_ME * ORC_C * ORC_C * ORC_C * ORC_C * ORC_C);
     for (int i = 0; i < 3; ++i) duRR[i] = -coef * v[i] * Q / (ORC_ME * ORC_C);
-    *chi = gam * sqrt(Q) / orc_critical_field();
+    *chi = gam * sqrt(Q) / orc_ecr();
 }
 
-static void orc_rhs_rr(const orc_laser* L, int rr, double t, const double Y[6], double dY[6],
-                       double* chi)
+void orc_rr_terms(const orc_laser* L, double t, const double Y[6], double duRR[3], double* chi)
 {
-    double du[3];
+    orc_real Yr[6], du[3], c;
+    for (int i = 0; i < 6; ++i) Yr[i] = Y[i];
+    orc_rr_terms_r(L, t, Yr, du, &c);
+    for (int i = 0; i < 3; ++i) duRR[i] = (double)du[i];
+    *chi = (double)c;
+}
+
+static void orc_rhs_rr(const orc_laser* L, int rr, orc_real t, const orc_real Y[6],
+                       orc_real dY[6], orc_real* chi)
+{
+    orc_real du[3];
     orc_rhs(L, t, Y, dY);
-    orc_rr_terms(L, t, Y, du, chi);
+    orc_rr_terms_r(L, t, Y, du, chi);
     if (rr)
         for (int i = 0; i < 3; ++i) dY[3 + i] += du[i];
 }
 
-void orc_push_one_rr(const orc_laser* L, int rr, double t0, double t_end, double h,
-                     const double x0[3], const double u0[3], double xf[3], double uf[3],
-                     double* chi_max)
+static void orc_push_elec_rr(const orc_laser* L, int rr, orc_real t0, orc_real t_end,
+                             orc_real h, const orc_real x0[3], const orc_real u0[3],
+                             orc_real xf[3], orc_real uf[3], orc_real* chi_max)
 {
-    double Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
-    double cm = 0.0;
+    orc_real Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
+    orc_real cm = 0.0;
     const int64_t N = (int64_t)ceil((t_end - t0) / h);
     for (int64_t n = 0; n < N; ++n) {
-        double ta = t0 + (double)n * h;
-        double hn = (n == N - 1) ? t_end - ta : h;
-        double k1[6], k2[6], k3[6], k4[6], Yt[6], chi, dummy;
+        orc_real ta = t0 + (orc_real)n * h;
+        orc_real hn = (n == N - 1) ? t_end - ta : h;
+        orc_real k1[6], k2[6], k3[6], k4[6], Yt[6], chi, dummy;
         orc_rhs_rr(L, rr, ta, Y, k1, &chi);
         if (chi > cm) cm = chi;
         for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];
@@ -783,6 +920,16 @@ void orc_push_one_rr(const orc_laser* L, int rr, double t0, double t_end, double
     *chi_max = cm;
 }
 
+void orc_push_one_rr(const orc_laser* L, int rr, double t0, double t_end, double h,
+                     const double x0[3], const double u0[3], double xf[3], double uf[3],
+                     double* chi_max)
+{
+    orc_real X0[3] = {x0[0], x0[1], x0[2]}, U0[3] = {u0[0], u0[1], u0[2]}, XF[3], UF[3], cm;
+    orc_push_elec_rr(L, rr, t0, t_end, h, X0, U0, XF, UF, &cm);
+    for (int i = 0; i < 3; ++i) { xf[i] = (double)XF[i]; uf[i] = (double)UF[i]; }
+    *chi_max = (double)cm;
+}
+
 void orc_push_rr(const orc_laser* L, int rr, int64_t n_slots, const double* t_birth,
                  const double* x0, const double* y0, const double* z0, int slots_per_atom,
                  double* ux, double* uy, double* uz, double* xf, double* yf, double* zf,
@@ -792,16 +939,17 @@ void orc_push_rr(const orc_laser* L, int rr, int64_t n_slots, const double* t_bi
     for (int64_t s = 0; s < n_slots; ++s) {
         int64_t a = s / slots_per_atom;
         double t0 = t_birth[s];
-        double ts, te;
+        orc_real ts, te;
         orc_window(L, z0[a], &ts, &te);
         if (!(t0 < INFINITY) || !(t0 >= ts - L->dt)) {
             ux[s] = uy[s] = uz[s] = xf[s] = yf[s] = zf[s] = chi_max[s] = NAN;
             continue;
         }
-        double X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
-        orc_push_one_rr(L, rr, t0, te, L->dt, X0, U0, XF, UF, &chi_max[s]);
-        ux[s] = UF[0]; uy[s] = UF[1]; uz[s] = UF[2];
-        xf[s] = XF[0]; yf[s] = XF[1]; zf[s] = XF[2];
+        orc_real X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3], cm;
+        orc_push_elec_rr(L, rr, t0, te, L->dt, X0, U0, XF, UF, &cm);
+        ux[s] = (double)UF[0]; uy[s] = (double)UF[1]; uz[s] = (double)UF[2];
+        xf[s] = (double)XF[0]; yf[s] = (double)XF[1]; zf[s] = (double)XF[2];
+        chi_max[s] = (double)cm;
     }
 }
 
@@ -850,7 +998,7 @@ static const double DP_B5[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0
 static const double DP_B4[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
                                 -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
 
-static double orc_gamma6(const double Y[6])
+static orc_real orc_gamma6(const orc_real Y[6])
 {
     return sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
 }
@@ -860,24 +1008,24 @@ int orc_push_one_adaptive(const orc_laser* L, const orc_adaptive* A, double t0, 
                           const double x0[3], const double u0[3], double xf[3], double uf[3],
                           double* t_stop, int64_t* n_acc, int64_t* n_rej)
 {
-    const double k = 2.0 * ORC_PI / L->lambda;
-    const double T = L->lambda / ORC_C;
-    const double scale[6] = {k, k, k, 1.0, 1.0, 1.0};
-    double Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
-    double K[7][6], Yt[6], Y5[6];
-    double t = t0, h = L->dt;
-    double g_ref = orc_gamma6(Y), t_ref = t0;
+    const orc_real k = 2.0 * ORC_PI / L->lambda;
+    const orc_real T = L->lambda / ORC_C;
+    const orc_real scale[6] = {k, k, k, 1.0, 1.0, 1.0};
+    orc_real Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
+    orc_real K[7][6], Yt[6], Y5[6];
+    orc_real t = t0, h = L->dt;
+    orc_real g_ref = orc_gamma6(Y), t_ref = t0;
     int64_t acc = 0, rej = 0;
     int status = 0;
     orc_rhs(L, t, Y, K[0]);
     while (t < t_end) {
         if (acc + rej >= A->max_steps) { status = 1; break; }
-        double hs = h < A->h_max ? h : A->h_max;
+        orc_real hs = h < A->h_max ? h : A->h_max;
         int last = 0;
         if (hs >= t_end - t) { hs = t_end - t; last = 1; }
         for (int s = 1; s < 7; ++s) {
             for (int i = 0; i < 6; ++i) {
-                double acc_i = 0.0;
+                orc_real acc_i = 0.0;
                 for (int j = 0; j < s; ++j) acc_i += DP_A[s][j] * K[j][i];
                 Yt[i] = Y[i] + hs * acc_i;
             }
@@ -885,13 +1033,13 @@ int orc_push_one_adaptive(const orc_laser* L, const orc_adaptive* A, double t0, 
         }
         /* stage 7 was evaluated at the fifth-order result (row 7 = b5) */
         for (int i = 0; i < 6; ++i) Y5[i] = Yt[i];
-        double err = 0.0;
+        orc_real err = 0.0;
         for (int i = 0; i < 6; ++i) {
-            double e = 0.0;
+            orc_real e = 0.0;
             for (int j = 0; j < 7; ++j) e += (DP_B5[j] - DP_B4[j]) * K[j][i];
             e = fabs(hs * e) * scale[i];
-            const double ya = fabs(Y[i]) * scale[i], yb = fabs(Y5[i]) * scale[i];
-            const double r = e / (A->atol + A->rtol * (ya > yb ? ya : yb));
+            const orc_real ya = fabs(Y[i]) * scale[i], yb = fabs(Y5[i]) * scale[i];
+            const orc_real r = e / (A->atol + A->rtol * (ya > yb ? ya : yb));
             if (r > err || r != r) err = r;
         }
         if (err != err) { status = 1; break; }   /* the step produced no number */
@@ -901,7 +1049,7 @@ int orc_push_one_adaptive(const orc_laser* L, const orc_adaptive* A, double t0, 
             ++acc;
             if (last) break;
             if (t - t_ref >= 0.999 * T) {
-                const double g = orc_gamma6(Y);
+                const orc_real g = orc_gamma6(Y);
                 if (fabs(g - g_ref) <= A->k_tol * g) break;
                 g_ref = g;
                 t_ref = t;
@@ -909,13 +1057,13 @@ int orc_push_one_adaptive(const orc_laser* L, const orc_adaptive* A, double t0, 
         } else {
             ++rej;
         }
-        double fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, -0.2);
+        orc_real fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, (orc_real)-0.2);
         if (fac > 5.0) fac = 5.0;
         if (fac < 0.2) fac = 0.2;
         h = hs * fac;
     }
-    for (int i = 0; i < 3; ++i) { xf[i] = Y[i]; uf[i] = Y[3 + i]; }
-    *t_stop = t;
+    for (int i = 0; i < 3; ++i) { xf[i] = (double)Y[i]; uf[i] = (double)Y[3 + i]; }
+    *t_stop = (double)t;
     *n_acc = acc;
     *n_rej = rej;
     if (status) {
@@ -935,7 +1083,7 @@ void orc_push_adaptive(const orc_laser* L, const orc_adaptive* A, int64_t n_slot
     for (int64_t s = 0; s < n_slots; ++s) {
         int64_t a = s / slots_per_atom;
         double t0 = t_birth[s];
-        double ts, te;
+        orc_real ts, te;
         orc_window(L, z0[a], &ts, &te);
         if (!(t0 < INFINITY) || !(t0 >= ts - L->dt)) {
             ux[s] = uy[s] = uz[s] = xf[s] = yf[s] = zf[s] = t_stop[s] = NAN;
@@ -943,7 +1091,8 @@ void orc_push_adaptive(const orc_laser* L, const orc_adaptive* A, int64_t n_slot
             continue;
         }
         double X0[3] = {x0[a], y0[a], z0[a]}, U0[3] = {0.0, 0.0, 0.0}, XF[3], UF[3];
-        orc_push_one_adaptive(L, A, t0, te, X0, U0, XF, UF, &t_stop[s], &n_acc[s], &n_rej[s]);
+        orc_push_one_adaptive(L, A, t0, (double)te, X0, U0, XF, UF, &t_stop[s], &n_acc[s],
+                              &n_rej[s]);
         ux[s] = UF[0]; uy[s] = UF[1]; uz[s] = UF[2];
         xf[s] = XF[0]; yf[s] = XF[1]; zf[s] = XF[2];
     }

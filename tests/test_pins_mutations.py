@@ -30,8 +30,8 @@ MUTANTS = [
     ("Philox Weyl constant", "W1 = 0xBB67AE8584CAA73BULL", "W1 = 0xBB67AE8584CAA73DULL", 0),
     ("uniform offset", "((double)m + 1.0)", "((double)m)", 0),
     ("uniform word", "out[j & 3]", "out[(j + 1) & 3]", 0),
-    ("sampler radius law", "double r = r_max * sqrt(u0);", "double r = r_max * u0;", 0),
-    ("sampler axial range", "z[i] = z_half * (2.0 * u2 - 1.0);", "z[i] = z_half * u2;", 0),
+    ("sampler radius law", "orc_real r = r_max * sqrt((orc_real)u0);", "orc_real r = r_max * u0;", 0),
+    ("sampler axial range", "*z = z_half * (2.0 * u2 - 1.0);", "*z = z_half * u2;", 0),
     # fields
     ("envelope sign", "exp(-rho2 / D - s * s)", "exp(-rho2 / D + 0.5 * s * s)", 0),
     ("wavefront curvature sign", "- rho2 * zeta / D;", "+ rho2 * zeta / D;", 0),
@@ -44,30 +44,31 @@ MUTANTS = [
     ("order-5 Er coefficient", "17.0 * r4 * C[6] / 16.0", "15.0 * r4 * C[6] / 16.0", 0),
     ("order-5 Bt coefficient", "- r6 * C[7] / 4.0 + r8 * C[8] / 32.0);",
      "- r6 * C[7] / 8.0 + r8 * C[8] / 32.0);", 0),
-    ("order-1 Ez sign", "double Ez = eps * (S[2] - r2 * S[3]);",
-     "double Ez = eps * (S[2] + r2 * S[3]);", 0),
+    ("order-1 Ez sign", "orc_real Ez = eps * (S[2] - r2 * S[3]);",
+     "orc_real Ez = eps * (S[2] + r2 * S[3]);", 0),
     ("B_x sign", "B[0] = -PB * y / (w0 * ORC_C);", "B[0] = PB * y / (w0 * ORC_C);", 0),
     ("Ez scale", "E[2] = L->ez_scale * Ez;", "E[2] = L->er_scale * Ez;", 0),
     ("plane-wave B sign", "B[1] = ex / ORC_C;", "B[1] = -ex / ORC_C;", 0),
-    ("tau0 from FWHM", "L->tau_fwhm / sqrt(2.0 * log(2.0))", "L->tau_fwhm / sqrt(log(2.0))", 0),
+    ("tau0 from FWHM", "L->tau_fwhm / sqrt(2.0 * log((orc_real)2.0))",
+     "L->tau_fwhm / sqrt(log((orc_real)2.0))", 0),
     # tunnelling rate
     ("ADK Gamma argument", "lgamma(2.0 * nstar)", "lgamma(nstar)", 0),
     ("ADK field exponent", "(2.0 * nstar - 1.0) * log(2.0 * F0 / F_au)",
      "(2.0 * nstar) * log(2.0 * F0 / F_au)", 0),
     ("ADK exponential", "- 2.0 * F0 / (3.0 * F_au);", "- F0 / (3.0 * F_au);", 0),
-    ("ADK charge of state k", "orc_adk_lnrate_general(Ip, (double)k, Emag / ORC_EA)",
-     "orc_adk_lnrate_general(Ip, (double)k - 0.5, Emag / ORC_EA)", 0),
+    ("ADK charge of state k", "orc_adk_lnrate_r(Ip, (orc_real)k, Emag / ORC_EA)",
+     "orc_adk_lnrate_r(Ip, (orc_real)k - 0.5, Emag / ORC_EA)", 0),
     ("ADK potential of state k", "orc_ne_ip_ev[k - 1] / ORC_EH_EV",
      "orc_ne_ip_ev[k < 10 ? k : 9] / ORC_EH_EV", 0),
     # quadrature and ionization
-    ("GL-4 weight", "double wa = (18.0 + sqrt(30.0)) / 36.0;",
-     "double wa = (18.0 + sqrt(30.0)) / 35.0;", 0),
-    ("GL-4 half width", "double h = 0.5 * (b - a), m = 0.5 * (a + b);",
-     "double h = (b - a), m = 0.5 * (a + b);", 0),
-    ("first threshold stream", "-log(orc_uniform(seed, cfg, atom, k_first + 2))",
-     "-log(orc_uniform(seed, cfg, atom, k_first + 3))", 0),
-    ("next threshold stream", "-log(orc_uniform(seed, cfg, atom, k_first + s + 2))",
-     "-log(orc_uniform(seed, cfg, atom, k_first + s + 1))", 0),
+    ("GL-4 weight", "orc_real wa = (18.0 + sqrt(thirty)) / 36.0;",
+     "orc_real wa = (18.0 + sqrt(thirty)) / 35.0;", 0),
+    ("GL-4 half width", "orc_real h = 0.5 * (b - a), m = 0.5 * (a + b);",
+     "orc_real h = (b - a), m = 0.5 * (a + b);", 0),
+    ("first threshold stream", "orc_uniform(seed, cfg, atom, k_first + 2)",
+     "orc_uniform(seed, cfg, atom, k_first + 3)", 0),
+    ("next threshold stream", "orc_uniform(seed, cfg, atom, k_first + s + 2)",
+     "orc_uniform(seed, cfg, atom, k_first + s + 1)", 0),
     ("integral not reset at a birth", "I = 0.0;\n                tstart = t;",
      "tstart = t;", 0),
     ("next state starts at window start", "I = 0.0;\n                tstart = t;",
@@ -81,10 +82,10 @@ MUTANTS = [
     ("RK4 weights", "(k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i])",
      "(k1[i] + 2.0 * k2[i] + k3[i] + 2.0 * k4[i])", 0),
     ("RK4 stage time", "orc_rhs(L, ta + 0.5 * hn, Yt, k2);", "orc_rhs(L, ta, Yt, k2);", 0),
-    ("RK4 last step", "double hn = (n == N - 1) ? t_end - ta : h;", "double hn = h;", 0),
+    ("RK4 last step", "orc_real hn = (n == N - 1) ? t_end - ta : h;", "orc_real hn = h;", 0),
     ("magnetic force sign", "dY[5] = q * (E[2] + (vx * B[1] - vy * B[0]));",
      "dY[5] = q * (E[2] - (vx * B[1] - vy * B[0]));", 0),
-    ("missing 1/gamma", "double vx = ORC_C * Y[3] / gam,", "double vx = ORC_C * Y[3],", 0),
+    ("missing 1/gamma", "orc_real vx = ORC_C * Y[3] / gam,", "orc_real vx = ORC_C * Y[3],", 0),
     ("before-window births accepted", "if (!(t0 >= ts - L->dt)) {",
      "if (!(t0 >= ts - 1e3 * L->dt)) {", 0),
     # outputs
@@ -110,10 +111,10 @@ MUTANTS = [
     # controlled-step push
     ("tableau entry", "44.0 / 45.0", "44.0 / 46.0", 0),
     ("embedded weight", "393.0 / 640.0", "393.0 / 641.0", 0),
-    ("controller exponent", "0.9 * pow(err, -0.2)", "0.9 * pow(err, -0.25)", 0),
+    ("controller exponent", "0.9 * pow(err, (orc_real)-0.2)", "0.9 * pow(err, (orc_real)-0.25)", 0),
     ("accept threshold", "if (err <= 1.0) {", "if (err <= 2.0) {", 0),
-    ("error scaling", "const double scale[6] = {k, k, k, 1.0, 1.0, 1.0};",
-     "const double scale[6] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0};", 0),
+    ("error scaling", "const orc_real scale[6] = {k, k, k, 1.0, 1.0, 1.0};",
+     "const orc_real scale[6] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0};", 0),
     ("stop rule", "if (fabs(g - g_ref) <= A->k_tol * g) break;",
      "if (fabs(g - g_ref) <= 1e3 * A->k_tol * g) break;", 0),
     ("check interval", "if (t - t_ref >= 0.999 * T) {", "if (t - t_ref >= 0.5 * T) {", 0),
@@ -172,3 +173,14 @@ def test_mutation_site_exists(label, old, new, nth):
     would make a mutant identical to the oracle)."""
     src = open(SRC).read()
     assert _mutate(src, old, new, nth) != src
+
+
+def test_pins_hold_for_extended_build():
+    """The extended-precision build of the oracle (the same source, every
+    step in x87 extended precision) is the reference that decides which
+    double results are determined to a tolerance at all, so it must pass the
+    same pins as the plain build."""
+    import oracle
+    oracle.build(force=False)
+    rc, out = _run_pins(os.path.join(ROOT, "oracle", "liborc_ext.so"), timeout=900)
+    assert rc == 0, out
