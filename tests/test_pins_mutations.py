@@ -86,6 +86,7 @@ MUTANTS = [
     ("magnetic force sign", "dY[5] = q * (E[2] + (vx * B[1] - vy * B[0]));",
      "dY[5] = q * (E[2] - (vx * B[1] - vy * B[0]));", 0),
     ("missing 1/gamma", "orc_real vx = ORC_C * Y[3] / gam,", "orc_real vx = ORC_C * Y[3],", 0),
+    ("state accumulation not compensated", "*comp = (t - *sum) - y;", "*comp = 0.0;", 0),
     ("before-window births accepted", "if (!(t0 >= ts - L->dt)) {",
      "if (!(t0 >= ts - 1e3 * L->dt)) {", 0),
     # outputs
