@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 _LIB_EXT = os.path.join(_HERE, "liborc_ext.so")
 
 RP_O1, RP_O3, RP_O5, PLANE_LP, UNIFORM_EB = 1, 3, 5, 10, 11
+LP_O1, LP_O3, LP_O5 = 21, 23, 25
 WIN_ARRIVAL, WIN_LAB = 0, 1
 ANG_POLAR, ANG_AZIMUTH = 0, 1
 
@@ -263,11 +264,14 @@ def push_one(L: Laser, t0, t_end, h, x0, u0):
     return xf, uf
 
 
-def push(L: Laser, t_birth, x0, y0, z0, slots_per_atom):
+def push(L: Laser, t_birth, x0, y0, z0, slots_per_atom, extended=False):
+    """FP64 push of every slot (extended=True: the extended-precision build,
+    same double inputs and outputs)."""
     t_birth = _d(t_birth)
     n = t_birth.size
     out = [np.zeros(n) for _ in range(6)]
-    lib().orc_push(C.byref(L), n, t_birth, _d(x0), _d(y0), _d(z0), slots_per_atom, *out)
+    (lib_extended() if extended else lib()).orc_push(C.byref(L), n, t_birth, _d(x0), _d(y0),
+                                                     _d(z0), slots_per_atom, *out)
     return tuple(out)  # ux, uy, uz, xf, yf, zf
 
 
@@ -334,14 +338,14 @@ def push_one_rr(L: Laser, rr, t0, t_end, h, x0, u0):
     return xf, uf, float(cm[0])
 
 
-def push_rr(L: Laser, rr, t_birth, x0, y0, z0, slots_per_atom):
+def push_rr(L: Laser, rr, t_birth, x0, y0, z0, slots_per_atom, extended=False):
     """Like push() with Eq. (3)'s radiation term on (rr=1) or off, plus the
     per-electron maximum of chi: (ux, uy, uz, xf, yf, zf, chi_max)."""
     t_birth = _d(t_birth)
     n = t_birth.size
     out = [np.zeros(n) for _ in range(7)]
-    lib().orc_push_rr(C.byref(L), int(rr), n, t_birth, _d(x0), _d(y0), _d(z0), slots_per_atom,
-                      *out)
+    (lib_extended() if extended else lib()).orc_push_rr(
+        C.byref(L), int(rr), n, t_birth, _d(x0), _d(y0), _d(z0), slots_per_atom, *out)
     return tuple(out)
 
 

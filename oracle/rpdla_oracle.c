@@ -87,7 +87,8 @@ static const orc_real orc_ne_ip_ev[10] = {
 
 /* field models */
 enum { ORC_RP_O1 = 1, ORC_RP_O3 = 3, ORC_RP_O5 = 5,
-       ORC_PLANE_LP = 10, ORC_UNIFORM_EB = 11 };
+       ORC_PLANE_LP = 10, ORC_UNIFORM_EB = 11,
+       ORC_LP_O1 = 21, ORC_LP_O3 = 23, ORC_LP_O5 = 25 };
 /* integration window */
 enum { ORC_WIN_ARRIVAL = 0, ORC_WIN_LAB = 1 };
 /* histogram angle */
@@ -283,8 +284,144 @@ void orc_sample_atoms(uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t 
  * Test models: a linearly polarized plane wave Ex = A env cos(omega t - k z
  * + phi0), By = Ex/c, and uniform static E and B.
  * ------------------------------------------------------------------------- */
-static void orc_field(const orc_laser* L, orc_real x, orc_real y, orc_real z, orc_real t,
-                      orc_real E[3], orc_real B[3])
+/* ---------------------------------------------------------------------------
+ * Linearly polarized focus (Sec. 2.2 compares the radially polarized pulse
+ * with a linearly polarized one of the same intensity, wavelength and focus,
+ * Fig. 4; the paper gives no field for it).  Reading: the same construction
+ * as the radial focus with the vector potential along x instead of z,
+ *     A = x^ (i E0 / omega) psi(rho, zeta) exp(i eta),  eta = omega t - k z + phi0,
+ * the same Lax series psi = psi0 + eps^2 psi2 + eps^4 psi4 (orders 1, 3, 5:
+ * the series truncated after psi0, psi2, psi4), Lorenz gauge
+ * (phi = (i c^2/omega) dA_x/dx), E = -grad phi - dA/dt, B = curl A, physical
+ * fields the real parts, times the same temporal envelope.  With
+ * s = rho^2 = (x^2 + y^2)/w0^2, rx = x/w0, ry = y/w0 and the derivatives of
+ * psi with respect to s and zeta (subscripts):
+ *   Ex = E0 Re{[psi + (eps^2/2) psi_s + eps^2 rx^2 psi_ss] e^{i eta}}
+ *   Ey = E0 Re{eps^2 rx ry psi_ss e^{i eta}}
+ *   Ez = E0 Re{[(eps^3/2) rx psi_s,zeta - i eps rx psi_s] e^{i eta}}
+ *   c Bx = 0,  c By = E0 Re{[psi + i (eps^2/2) psi_zeta] e^{i eta}},
+ *   c Bz = E0 Re{-i eps ry psi_s e^{i eta}}.
+ * E0 is the peak field at the focus of the paraxial beam, so the amplitude
+ * from intensity, sqrt(2 I / (eps0 c)), gives peak intensity I.  The
+ * derivatives of psi are taken exactly by hyper-dual arithmetic (numbers
+ * a + b e1 + c e2 + d e1 e2 with e1^2 = e2^2 = 0, complex parts): evaluating
+ * psi at s + e1 + e2 gives psi_s in b and psi_ss in d, at (s + e1, zeta + e2)
+ * psi_zeta in c and psi_s,zeta in d.
+ * ------------------------------------------------------------------------- */
+#ifdef ORC_EXTENDED
+typedef long double _Complex orc_cplx;
+#else
+typedef double _Complex orc_cplx;
+#endif
+typedef struct { orc_cplx a, b, c, d; } orc_hd;
+
+static orc_hd hd_make(orc_cplx a, orc_cplx b, orc_cplx c)
+{
+    orc_hd r = {a, b, c, 0};
+    return r;
+}
+
+static orc_hd hd_add(orc_hd x, orc_hd y)
+{
+    orc_hd r = {x.a + y.a, x.b + y.b, x.c + y.c, x.d + y.d};
+    return r;
+}
+
+static orc_hd hd_scale(orc_hd x, orc_cplx k)
+{
+    orc_hd r = {k * x.a, k * x.b, k * x.c, k * x.d};
+    return r;
+}
+
+static orc_hd hd_mul(orc_hd x, orc_hd y)
+{
+    orc_hd r = {x.a * y.a, x.a * y.b + x.b * y.a, x.a * y.c + x.c * y.a,
+                x.a * y.d + x.b * y.c + x.c * y.b + x.d * y.a};
+    return r;
+}
+
+static orc_hd hd_exp(orc_hd x)
+{
+    orc_cplx e = exp(x.a);
+    orc_hd r = {e, e * x.b, e * x.c, e * (x.d + x.b * x.c)};
+    return r;
+}
+
+static orc_hd hd_inv(orc_hd x)
+{
+    orc_cplx q = 1.0 / x.a;
+    orc_hd r = {q, -q * q * x.b, -q * q * x.c, 2.0 * q * q * q * x.b * x.c - q * q * x.d};
+    return r;
+}
+
+static orc_hd hd_pow(orc_hd x, int n)
+{
+    orc_hd r = hd_make(1.0, 0.0, 0.0);
+    for (int i = 0; i < n; ++i) r = hd_mul(r, x);
+    return r;
+}
+
+/* The Lax series psi(s, zeta) truncated at `order` (1, 3 or 5):
+ *   f = 1/(1 - i zeta),  psi0 = f e^{-f s},
+ *   psi2 = (f^2/2 - f^4 s^2/4) e^{-f s},
+ *   psi4 = (3f^3/8 - 3f^5 s^2/16 - f^6 s^3/8 + f^7 s^4/32) e^{-f s}. */
+static orc_hd orc_lax_psi(orc_hd S, orc_hd Zt, orc_real eps, int order)
+{
+    const orc_cplx iu = (orc_cplx)_Complex_I;
+    orc_hd one = hd_make(1.0, 0.0, 0.0);
+    orc_hd f = hd_inv(hd_add(one, hd_scale(Zt, -iu)));
+    orc_hd P = f;
+    if (order >= 3) {
+        orc_hd p2 = hd_add(hd_scale(hd_pow(f, 2), 0.5),
+                           hd_scale(hd_mul(hd_pow(f, 4), hd_pow(S, 2)), -0.25));
+        P = hd_add(P, hd_scale(p2, eps * eps));
+    }
+    if (order >= 5) {
+        orc_hd p4 = hd_scale(hd_pow(f, 3), 3.0 / 8.0);
+        p4 = hd_add(p4, hd_scale(hd_mul(hd_pow(f, 5), hd_pow(S, 2)), -3.0 / 16.0));
+        p4 = hd_add(p4, hd_scale(hd_mul(hd_pow(f, 6), hd_pow(S, 3)), -1.0 / 8.0));
+        p4 = hd_add(p4, hd_scale(hd_mul(hd_pow(f, 7), hd_pow(S, 4)), 1.0 / 32.0));
+        P = hd_add(P, hd_scale(p4, eps * eps * eps * eps));
+    }
+    return hd_mul(P, hd_exp(hd_scale(hd_mul(f, S), -1.0)));
+}
+
+static void orc_field_lp(const orc_laser* L, orc_real x, orc_real y, orc_real z, orc_real xi,
+                         orc_real E[3], orc_real B[3])
+{
+    const orc_cplx iu = (orc_cplx)_Complex_I;
+    const orc_real k = 2.0 * ORC_PI / L->lambda;
+    const orc_real om = ORC_C * k;
+    const orc_real tau0 = L->tau_fwhm / sqrt(2.0 * log((orc_real)2.0));
+    const int order = L->field - 20;
+    const orc_real w0 = L->w0;
+    const orc_real zr = 0.5 * k * w0 * w0;
+    const orc_real eps = w0 / zr;
+    const orc_real rx = x / w0, ry = y / w0;
+    const orc_real s = rx * rx + ry * ry;
+    const orc_real zeta = z / zr;
+    /* psi, psi_s, psi_ss */
+    orc_hd ps = orc_lax_psi(hd_make(s, 1.0, 1.0), hd_make(zeta, 0.0, 0.0), eps, order);
+    /* psi_zeta, psi_s,zeta */
+    orc_hd pz = orc_lax_psi(hd_make(s, 1.0, 0.0), hd_make(zeta, 0.0, 1.0), eps, order);
+    const orc_cplx psi = ps.a, psi_s = ps.b, psi_ss = ps.d, psi_z = pz.c, psi_sz = pz.d;
+    const orc_real sg = xi / tau0;
+    const orc_real amp = L->amp * exp(-sg * sg);
+    const orc_cplx ph = exp(iu * (om * xi + L->phi0));
+    const orc_real e2 = eps * eps;
+    E[0] = L->er_scale * amp * creal((psi + 0.5 * e2 * psi_s + e2 * rx * rx * psi_ss) * ph);
+    E[1] = L->er_scale * amp * creal(e2 * rx * ry * psi_ss * ph);
+    E[2] = L->ez_scale * amp * creal((0.5 * e2 * eps * rx * psi_sz - iu * eps * rx * psi_s) * ph);
+    B[0] = 0.0;
+    B[1] = amp / ORC_C * creal((psi + iu * 0.5 * e2 * psi_z) * ph);
+    B[2] = amp / ORC_C * creal(-iu * eps * ry * psi_s * ph);
+}
+
+/* Every field family depends on time only through the retarded time
+ * xi = t - z/c (carrier phase omega xi, envelope xi/tau0); orc_field_ret takes
+ * xi itself, orc_field the time t. */
+static void orc_field_ret(const orc_laser* L, orc_real x, orc_real y, orc_real z, orc_real xi,
+                          orc_real E[3], orc_real B[3])
 {
     const orc_real k = 2.0 * ORC_PI / L->lambda;
     const orc_real om = ORC_C * k;
@@ -293,9 +430,13 @@ static void orc_field(const orc_laser* L, orc_real x, orc_real y, orc_real z, or
         for (int i = 0; i < 3; ++i) { E[i] = L->test_E[i]; B[i] = L->test_B[i]; }
         return;
     }
+    if (L->field == ORC_LP_O1 || L->field == ORC_LP_O3 || L->field == ORC_LP_O5) {
+        orc_field_lp(L, x, y, z, xi, E, B);
+        return;
+    }
     if (L->field == ORC_PLANE_LP) {
-        orc_real s = (t - z / ORC_C) / tau0;
-        orc_real ex = L->amp * exp(-s * s) * cos(om * t - k * z + L->phi0);
+        orc_real s = xi / tau0;
+        orc_real ex = L->amp * exp(-s * s) * cos(om * xi + L->phi0);
         E[0] = ex; E[1] = 0.0; E[2] = 0.0;
         B[0] = 0.0; B[1] = ex / ORC_C; B[2] = 0.0;
         return;
@@ -307,8 +448,8 @@ static void orc_field(const orc_laser* L, orc_real x, orc_real y, orc_real z, or
     const orc_real rho2 = (x * x + y * y) / (w0 * w0);
     const orc_real zeta = z / zr;
     const orc_real D = 1.0 + zeta * zeta;
-    const orc_real Psi = L->phi0 + om * t - k * z - rho2 * zeta / D;
-    const orc_real s = (t - z / ORC_C) / tau0;
+    const orc_real Psi = L->phi0 + om * xi - rho2 * zeta / D;
+    const orc_real s = xi / tau0;
     const orc_real g = exp(-rho2 / D - s * s);
     const orc_real gouy = atan(zeta);
     orc_real C[9], S[9];
@@ -341,6 +482,12 @@ static void orc_field(const orc_laser* L, orc_real x, orc_real y, orc_real z, or
     B[0] = -PB * y / (w0 * ORC_C);
     B[1] = PB * x / (w0 * ORC_C);
     B[2] = 0.0;
+}
+
+static void orc_field(const orc_laser* L, orc_real x, orc_real y, orc_real z, orc_real t,
+                      orc_real E[3], orc_real B[3])
+{
+    orc_field_ret(L, x, y, z, t - z / ORC_C, E, B);
 }
 
 /* ---------------------------------------------------------------------------
@@ -545,6 +692,14 @@ void orc_ionize(const orc_laser* L, uint64_t seed, uint32_t cfg, uint64_t first_
  * (their trajectories amplify rounding by up to ~1e8; measured against the
  * extended-precision build), and compensation removes that part of the
  * rounding error.
+ *
+ * The fields depend on time only through the retarded time xi = t - z/c,
+ * and the state carries xi as a seventh variable, d xi/dt = 1 - v_z/c, from
+ * xi = t0 - z0/c.  RK4 is linear in the stage slopes, so in exact arithmetic
+ * its xi equals t - z/c at every stage and step: the discretized trajectory
+ * is the one of the six-variable system.  In floating point the carrier
+ * phase omega xi is then resolved to the rounding of xi itself instead of
+ * that of omega t and k z separately (each up to ~1e3 rad over the window).
  * ------------------------------------------------------------------------- */
 static void orc_kahan_add(orc_real* sum, orc_real* comp, orc_real v)
 {
@@ -554,10 +709,10 @@ static void orc_kahan_add(orc_real* sum, orc_real* comp, orc_real v)
     *sum = t;
 }
 
-static void orc_rhs(const orc_laser* L, orc_real t, const orc_real Y[6], orc_real dY[6])
+/* Slopes of (x, u) for the fields E, B at the state; returns gamma. */
+static orc_real orc_lorentz(const orc_real Y[6], const orc_real E[3], const orc_real B[3],
+                            orc_real dY[6])
 {
-    orc_real E[3], B[3];
-    orc_field(L, Y[0], Y[1], Y[2], t, E, B);
     orc_real gam = sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
     orc_real vx = ORC_C * Y[3] / gam, vy = ORC_C * Y[4] / gam, vz = ORC_C * Y[5] / gam;
     const orc_real q = -ORC_QE / (ORC_ME * ORC_C);
@@ -565,27 +720,45 @@ static void orc_rhs(const orc_laser* L, orc_real t, const orc_real Y[6], orc_rea
     dY[3] = q * (E[0] + (vy * B[2] - vz * B[1]));
     dY[4] = q * (E[1] + (vz * B[0] - vx * B[2]));
     dY[5] = q * (E[2] + (vx * B[1] - vy * B[0]));
+    return gam;
+}
+
+/* Six-variable right-hand side at time t (the controlled-step push). */
+static void orc_rhs(const orc_laser* L, orc_real t, const orc_real Y[6], orc_real dY[6])
+{
+    orc_real E[3], B[3];
+    orc_field(L, Y[0], Y[1], Y[2], t, E, B);
+    orc_lorentz(Y, E, B, dY);
+}
+
+/* Seven-variable right-hand side: Y[6] = xi = t - z/c. */
+static void orc_rhs_xi(const orc_laser* L, const orc_real Y[7], orc_real dY[7])
+{
+    orc_real E[3], B[3];
+    orc_field_ret(L, Y[0], Y[1], Y[2], Y[6], E, B);
+    const orc_real gam = orc_lorentz(Y, E, B, dY);
+    dY[6] = 1.0 - Y[5] / gam;
 }
 
 static void orc_push_elec(const orc_laser* L, orc_real t0, orc_real t_end, orc_real h,
                           const orc_real x0[3], const orc_real u0[3], orc_real xf[3],
                           orc_real uf[3])
 {
-    orc_real Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
-    orc_real comp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    orc_real Y[7] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2], t0 - x0[2] / ORC_C};
+    orc_real comp[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int64_t N = (int64_t)ceil((t_end - t0) / h);
     for (int64_t n = 0; n < N; ++n) {
         orc_real ta = t0 + (orc_real)n * h;
         orc_real hn = (n == N - 1) ? t_end - ta : h;
-        orc_real k1[6], k2[6], k3[6], k4[6], Yt[6];
-        orc_rhs(L, ta, Y, k1);
-        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];
-        orc_rhs(L, ta + 0.5 * hn, Yt, k2);
-        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k2[i];
-        orc_rhs(L, ta + 0.5 * hn, Yt, k3);
-        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + hn * k3[i];
-        orc_rhs(L, ta + hn, Yt, k4);
-        for (int i = 0; i < 6; ++i)
+        orc_real k1[7], k2[7], k3[7], k4[7], Yt[7];
+        orc_rhs_xi(L, Y, k1);
+        for (int i = 0; i < 7; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];
+        orc_rhs_xi(L, Yt, k2);
+        for (int i = 0; i < 7; ++i) Yt[i] = Y[i] + 0.5 * hn * k2[i];
+        orc_rhs_xi(L, Yt, k3);
+        for (int i = 0; i < 7; ++i) Yt[i] = Y[i] + hn * k3[i];
+        orc_rhs_xi(L, Yt, k4);
+        for (int i = 0; i < 7; ++i)
             orc_kahan_add(&Y[i], &comp[i], hn / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]));
     }
     for (int i = 0; i < 3; ++i) { xf[i] = Y[i]; uf[i] = Y[3 + i]; }
@@ -871,12 +1044,13 @@ static orc_real orc_ecr(void)
 
 double orc_critical_field(void) { return (double)orc_ecr(); }
 
-/* du/dt of Eq. (3)'s radiation term (u = p / m c) and chi, for state Y at t. */
-static void orc_rr_terms_r(const orc_laser* L, orc_real t, const orc_real Y[6], orc_real duRR[3],
+/* du/dt of Eq. (3)'s radiation term (u = p / m c) and chi, for state Y at
+ * retarded time xi. */
+static void orc_rr_terms_r(const orc_laser* L, orc_real xi, const orc_real Y[6], orc_real duRR[3],
                            orc_real* chi)
 {
     orc_real E[3], B[3];
-    orc_field(L, Y[0], Y[1], Y[2], t, E, B);
+    orc_field_ret(L, Y[0], Y[1], Y[2], xi, E, B);
     const orc_real gam = sqrt(1.0 + Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]);
     const orc_real v[3] = {ORC_C * Y[3] / gam, ORC_C * Y[4] / gam, ORC_C * Y[5] / gam};
     const orc_real f[3] = {E[0] + (v[1] * B[2] - v[2] * B[1]),
@@ -896,17 +1070,17 @@ void orc_rr_terms(const orc_laser* L, double t, const double Y[6], double duRR[3
 {
     orc_real Yr[6], du[3], c;
     for (int i = 0; i < 6; ++i) Yr[i] = Y[i];
-    orc_rr_terms_r(L, t, Yr, du, &c);
+    orc_rr_terms_r(L, t - Yr[2] / ORC_C, Yr, du, &c);
     for (int i = 0; i < 3; ++i) duRR[i] = (double)du[i];
     *chi = (double)c;
 }
 
-static void orc_rhs_rr(const orc_laser* L, int rr, orc_real t, const orc_real Y[6],
-                       orc_real dY[6], orc_real* chi)
+static void orc_rhs_rr(const orc_laser* L, int rr, const orc_real Y[7], orc_real dY[7],
+                       orc_real* chi)
 {
     orc_real du[3];
-    orc_rhs(L, t, Y, dY);
-    orc_rr_terms_r(L, t, Y, du, chi);
+    orc_rhs_xi(L, Y, dY);
+    orc_rr_terms_r(L, Y[6], Y, du, chi);
     if (rr)
         for (int i = 0; i < 3; ++i) dY[3 + i] += du[i];
 }
@@ -915,23 +1089,23 @@ static void orc_push_elec_rr(const orc_laser* L, int rr, orc_real t0, orc_real t
                              orc_real h, const orc_real x0[3], const orc_real u0[3],
                              orc_real xf[3], orc_real uf[3], orc_real* chi_max)
 {
-    orc_real Y[6] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2]};
-    orc_real comp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    orc_real Y[7] = {x0[0], x0[1], x0[2], u0[0], u0[1], u0[2], t0 - x0[2] / ORC_C};
+    orc_real comp[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     orc_real cm = 0.0;
     const int64_t N = (int64_t)ceil((t_end - t0) / h);
     for (int64_t n = 0; n < N; ++n) {
         orc_real ta = t0 + (orc_real)n * h;
         orc_real hn = (n == N - 1) ? t_end - ta : h;
-        orc_real k1[6], k2[6], k3[6], k4[6], Yt[6], chi, dummy;
-        orc_rhs_rr(L, rr, ta, Y, k1, &chi);
+        orc_real k1[7], k2[7], k3[7], k4[7], Yt[7], chi, dummy;
+        orc_rhs_rr(L, rr, Y, k1, &chi);
         if (chi > cm) cm = chi;
-        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];
-        orc_rhs_rr(L, rr, ta + 0.5 * hn, Yt, k2, &dummy);
-        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + 0.5 * hn * k2[i];
-        orc_rhs_rr(L, rr, ta + 0.5 * hn, Yt, k3, &dummy);
-        for (int i = 0; i < 6; ++i) Yt[i] = Y[i] + hn * k3[i];
-        orc_rhs_rr(L, rr, ta + hn, Yt, k4, &dummy);
-        for (int i = 0; i < 6; ++i)
+        for (int i = 0; i < 7; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];
+        orc_rhs_rr(L, rr, Yt, k2, &dummy);
+        for (int i = 0; i < 7; ++i) Yt[i] = Y[i] + 0.5 * hn * k2[i];
+        orc_rhs_rr(L, rr, Yt, k3, &dummy);
+        for (int i = 0; i < 7; ++i) Yt[i] = Y[i] + hn * k3[i];
+        orc_rhs_rr(L, rr, Yt, k4, &dummy);
+        for (int i = 0; i < 7; ++i)
             orc_kahan_add(&Y[i], &comp[i], hn / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]));
     }
     for (int i = 0; i < 3; ++i) { xf[i] = Y[i]; uf[i] = Y[3 + i]; }

@@ -51,6 +51,15 @@ MUTANTS = [
     ("plane-wave B sign", "B[1] = ex / ORC_C;", "B[1] = -ex / ORC_C;", 0),
     ("tau0 from FWHM", "L->tau_fwhm / sqrt(2.0 * log((orc_real)2.0))",
      "L->tau_fwhm / sqrt(log((orc_real)2.0))", 0),
+    # linearly polarized focus
+    ("LP Ez sign", "- iu * eps * rx * psi_s) * ph);", "+ iu * eps * rx * psi_s) * ph);", 0),
+    ("LP Ex gauge term", "(psi + 0.5 * e2 * psi_s + e2 * rx * rx * psi_ss)", "(psi + e2 * rx * rx * psi_ss)", 0),
+    ("LP By correction", "(psi + iu * 0.5 * e2 * psi_z)", "(psi - iu * 0.5 * e2 * psi_z)", 0),
+    ("LP Bz component", "creal(-iu * eps * ry * psi_s * ph)", "creal(-iu * eps * rx * psi_s * ph)", 0),
+    ("LP series coefficient", "hd_scale(hd_pow(f, 3), 3.0 / 8.0)", "hd_scale(hd_pow(f, 3), 3.0 / 16.0)", 0),
+    ("hyper-dual exp", "e * (x.d + x.b * x.c)", "e * x.d", 0),
+    ("hyper-dual inverse", "-q * q * x.c,", "q * q * x.c,", 0),
+    ("hyper-dual product", "x.a * y.d + x.b * y.c + x.c * y.b + x.d * y.a", "x.a * y.d + x.b * y.c + x.d * y.a", 0),
     # tunnelling rate
     ("ADK Gamma argument", "lgamma(2.0 * nstar)", "lgamma(nstar)", 0),
     ("ADK field exponent", "(2.0 * nstar - 1.0) * log(2.0 * F0 / F_au)",
@@ -81,7 +90,10 @@ MUTANTS = [
     # push
     ("RK4 weights", "(k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i])",
      "(k1[i] + 2.0 * k2[i] + k3[i] + 2.0 * k4[i])", 0),
-    ("RK4 stage time", "orc_rhs(L, ta + 0.5 * hn, Yt, k2);", "orc_rhs(L, ta, Yt, k2);", 0),
+    ("RK4 stage state", "for (int i = 0; i < 7; ++i) Yt[i] = Y[i] + 0.5 * hn * k2[i];",
+     "for (int i = 0; i < 7; ++i) Yt[i] = Y[i] + 0.5 * hn * k1[i];", 0),
+    ("retarded-time slope", "dY[6] = 1.0 - Y[5] / gam;", "dY[6] = 1.0;", 0),
+    ("retarded-time start", "t0 - x0[2] / ORC_C};", "t0};", 0),
     ("RK4 last step", "orc_real hn = (n == N - 1) ? t_end - ta : h;", "orc_real hn = h;", 0),
     ("magnetic force sign", "dY[5] = q * (E[2] + (vx * B[1] - vy * B[0]));",
      "dY[5] = q * (E[2] - (vx * B[1] - vy * B[0]));", 0),
