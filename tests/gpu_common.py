@@ -28,38 +28,40 @@ def gpu_energy(B, torch, ux, uy, uz):
 def energy_parity(Kg, fg, Ko, fo):
     """Per electron: energies agree to 1e-8 relative (+1e-12 MeV); directions
     agree."""
-    ok = np.abs(Kg - Ko) <= 1e-8 * np.abs(Ko) + 1e-12
-    return ok, np.asarray(fg) == np.asarray(fo)
+    from oracle import parity
+    return parity.within(Kg, Ko), np.asarray(fg) == np.asarray(fo)
 
 
 def allowed_failures(n, frac=0.999):
-    return int(np.floor((1 - frac) * n))
+    from oracle import parity
+    return parity.allowed_misses(n, frac)
 
 
-def conditioned_energy_check(O, OL, otb, xs, ys, zs, K, Kg, fg, label="", shift_rel=1e-15):
-    """FP64 energy parity judged against the oracle's own conditioning.
-
-    otb, xs, ys, zs are the oracle's inputs (its own chain or seeded inputs);
-    Kg, fg the GPU's energies and forward flags for the born slots.  Electrons
-    whose oracle energy moves by less than 1e-10 when the birth times shift by
-    shift_rel max(|t|, T) must agree to 1e-8 (99.9%); the rest must agree
-    within 1e3 times that self-sensitivity (or 1e-8)."""
+def check_fp64_values(Kg, fg, Kop, fop, Kx=None, Koc=None, label=""):
+    """The FP64 energy rule (oracle/parity.py) on energies the caller computed
+    for the same born electrons; asserts and returns the verdict."""
     import sys
-    fin = np.isfinite(otb)
-    ref = O.push(OL, otb, xs, ys, zs, K)
-    Ko, _, _, fo = O.epilogue(*(r[fin] for r in ref[:3]))
-    T = OL.lambda_ / C_LIGHT
-    pert = O.push(OL, otb + np.where(fin, shift_rel * np.maximum(np.abs(otb), T), 0.0),
-                  xs, ys, zs, K)
-    Kp = O.epilogue(*(r[fin] for r in pert[:3]))[0]
-    kappa = np.abs(Kp - Ko) / Ko
-    rel = np.abs(Kg - Ko) / Ko
-    ok, same = energy_parity(Kg, fg, Ko, fo)
-    well = kappa < 1e-10
-    print(f"[parity{label}] {fin.sum()} electrons, max K {Ko.max():.3g} MeV; within 1e-8 "
-          f"{ok.mean():.4f} ({well.sum()} well-conditioned), max rel {rel.max():.1e}",
-          file=sys.stderr, flush=True)
-    assert (~ok[well]).sum() <= allowed_failures(well.sum()) + 1
-    assert np.all(rel[~well] <= np.maximum(1e-8, 1e3 * kappa[~well]))
-    assert (~same).sum() <= allowed_failures(fin.sum()) + 1
-    return ok, rel
+
+    from oracle import parity
+    v = parity.fp64_energy_verdict(Kg, fg, Kop, fop, Kx=Kx, Koc=Koc)
+    print(parity.summary(v, label), file=sys.stderr, flush=True)
+    assert v["passed"], v
+    return v
+
+
+def check_fp64(O, OL, Kg, fg, tb_gpu, xs, ys, zs, K, Kx=None, Koc=None, label="",
+               extended_push=False):
+    """The FP64 energy rule (oracle/parity.py) for the born slots of
+    per-slot arrays: the GPU's energies Kg and flags fg (born slots only),
+    tb_gpu the GPU's birth times of all slots, xs, ys, zs the atoms (slot s
+    belongs to atom s // K).  The double oracle pushes the same electrons from
+    the GPU's births; the extended reference is Kx (born slots), or, with
+    extended_push, the extended build's push of the same inputs.  Asserts
+    and returns the verdict."""
+    fin = np.isfinite(tb_gpu)
+    ref = O.push(OL, tb_gpu, xs, ys, zs, K)
+    Kop, _, _, fop = O.epilogue(*(r[fin] for r in ref[:3]))
+    if extended_push:
+        ext = O.push(OL, tb_gpu, xs, ys, zs, K, extended=True)
+        Kx = O.epilogue(*(r[fin] for r in ext[:3]))[0]
+    return check_fp64_values(Kg, fg, Kop, fop, Kx=Kx, Koc=Koc, label=label)

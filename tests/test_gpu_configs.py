@@ -11,7 +11,7 @@ import time
 import numpy as np
 import pytest
 
-from gpu_common import C_LIGHT, conditioned_energy_check, gpu_energy, require_gpu
+from gpu_common import C_LIGHT, allowed_failures, check_fp64, gpu_energy, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -50,61 +50,67 @@ def _oracle_laser(O, rec):
 
 
 def _batched_vs_single(torch, B, c, arr, tal_b, counts_b, single, n, K, label):
-    """Birth times and positions bit-identical (same FP64 kernels' inputs);
-    momenta agree to rounding, amplified only where trajectories are
-    ill-conditioned, so histograms and directions agree to a small fraction."""
+    """Element by element: positions and birth times bit-identical (the same
+    sampling and ionization arithmetic), final energies within 1e-8 of the
+    single-configuration push for >= 99.9% of the electrons and the same
+    direction for >= 99.9% (the two push kernels are separate compilations
+    of the same arithmetic, so their rounding differs), unborn and NaN tallies
+    equal."""
+    from oracle import parity
     (sc, st), (x, y, z, tb, out) = single
     st = st.cpu().numpy()
-    assert torch.equal(arr["x"][c, :n], x) and torch.equal(arr["t_birth"][c, :n].reshape(-1), tb)
+    assert torch.equal(arr["x"][c, :n], x) and torch.equal(arr["z"][c, :n], z)
+    assert torch.equal(arr["t_birth"][c, :n].reshape(-1), tb)
     assert st[4] == tal_b[c, 4] and st[5] == tal_b[c, 5] == 0         # unborn, NaN
-    born = int(st[0] + st[1])
     fin = torch.isfinite(tb)
-    u2 = lambda a, b, c_: a * a + b * b + c_ * c_
-    Kb = u2(arr["ux"][c, :n].reshape(-1)[fin], arr["uy"][c, :n].reshape(-1)[fin],
-            arr["uz"][c, :n].reshape(-1)[fin])
-    Ks = u2(out[0][fin], out[1][fin], out[2][fin])
-    rel = ((Kb - Ks).abs() / Ks.clamp(min=1e-300)).double()
+    Kb, fb = gpu_energy(B, torch, *(arr[k][c, :n].reshape(-1)[fin] for k in ("ux", "uy", "uz")))
+    Ks, fs = gpu_energy(B, torch, *(o[fin] for o in out[:3]))
+    ok = parity.within(Kb, Ks)
+    same = fb == fs
+    nb = int(fin.sum())
+    rel = np.abs(Kb - Ks) / Ks
     l1 = int((sc - counts_b[c]).abs().sum())
-    _log(f"{label} cfg {c}: {born} electrons; batched vs single |du^2|/u^2 median "
-         f"{float(rel.median()):.1e}, beyond 1e-8 {float((rel > 1e-8).double().mean()):.4f}; "
-         f"histogram L1 {l1}; forward {int(tal_b[c, 0])} vs {int(st[0])}")
-    assert float(rel.median()) < 1e-12
-    assert abs(int(tal_b[c, 0]) - int(st[0])) <= 0.01 * born + 2
-    assert l1 <= 0.05 * born + 4
+    _log(f"{label} cfg {c}: {nb} electrons; batched vs single: {(~ok).sum()} beyond 1e-8 "
+         f"(median {np.median(rel):.1e}, max {rel.max():.1e}), {(~same).sum()} direction "
+         f"changes, histogram L1 {l1}")
+    assert (~ok).sum() <= allowed_failures(nb)
+    assert (~same).sum() <= allowed_failures(nb)
 
 
-def _oracle_check_batched(O, OL, torch, arr, c, atoms, seed, cfg_id, r_factor, kf, kl, first,
-                          label, mixed=False):
+def _oracle_check_batched(O, OL, torch, B, arr, c, atoms, seed, cfg_id, r_factor, kf, kl, first,
+                          label, Kx=None, mixed=False):
     """Sampled atoms of the batched chunk (chunk start `first`) against the
-    oracle's own chain from the seed."""
-    from gpu_common import gpu_energy
+    oracle: positions and birth times from the oracle's own sampling and
+    ionization from the seed; FP64 energies by the rule of oracle/parity.py
+    (the double oracle's push of the same inputs, and the extended-precision
+    chain Kx when given); mixed energies against the double oracle."""
     K = kl - kf + 1
     idx = np.asarray(atoms)
     xs, ys, zs, otb = _oracle_atoms(O, OL, seed, cfg_id, first + idx, r_factor, kf, kl)
     loc = torch.as_tensor(idx, device="cuda")
-    assert np.max(np.abs(arr["x"][c][loc].cpu().numpy() - xs)) <= 1e-20
+    gx = [arr[k][c][loc].cpu().numpy() for k in ("x", "y", "z")]
+    assert np.max(np.abs(gx[0] - xs)) <= 1e-20
     gtb = arr["t_birth"][c][loc].cpu().numpy().ravel()
     fin = np.isfinite(otb)
     assert np.array_equal(fin, np.isfinite(gtb))
     T = OL.lambda_ / C_LIGHT
     assert np.all(np.abs(gtb[fin] - otb[fin]) <= 1e-10 * np.maximum(np.abs(otb[fin]), T))
     g = [arr[k][c][loc].cpu().numpy().ravel()[fin] for k in ("ux", "uy", "uz")]
-    Kg, fg = gpu_energy(B_, torch, *g)
+    Kg, fg = gpu_energy(B, torch, *g)
     if not mixed:
-        conditioned_energy_check(O, OL, otb, xs, ys, zs, K, Kg, fg, label=label)
-        return
-    ref = O.push(OL, otb, xs, ys, zs, K)
+        return Kg, fg, gtb, gx
+    ref = O.push(OL, gtb, *gx, K)
     Ko = O.epilogue(*(r[fin] for r in ref[:3]))[0]
     rel = np.abs(Kg - Ko) / Ko
     _log(f"{label}: {fin.sum()} electrons, mixed vs oracle median {np.median(rel):.1e}, "
-         f"max {rel.max():.1e}")
-    assert np.median(rel) < 1e-5 and np.mean(rel <= 1e-3) >= 0.9
+         f"within 1e-3 {np.mean(rel <= 1e-3):.4f}, max {rel.max():.1e}")
+    assert np.median(rel) < 1e-6 and np.mean(rel <= 1e-3) >= 0.98
+    return Kg, fg, gtb, gx
 
 
+@pytest.mark.timeout(900)
 def test_sweep64_full_size(env):
-    global B_
     torch, B, P, W, O = env
-    B_ = B
     wl = W.SWEEP_FP64
     n, K = wl["atoms"], wl["k_last"] - wl["k_first"] + 1
     n_cfg = len(wl["lasers"])
@@ -132,11 +138,37 @@ def test_sweep64_full_size(env):
         single = _single(B, L, wl["seed"], base + c, n, wl["k_first"], wl["k_last"],
                          wl["r_factor"], B.RPDLA_FP64, spec)
         _batched_vs_single(torch, B, c, arr, tal, counts, single, n, K, "sweep64")
-        OL = _oracle_laser(O, rec)
+    # every configuration: 64 sampled atoms against the oracle, element by
+    # element, under the FP64 rule (pooled over the configurations)
+    from golden.make_extended_refs import load
+    from oracle import parity
+    Kx_all, atoms_all, cfg_ids, cfgs = load("rp_ne_sweep64_sampled")
+    pool = {k: [] for k in ("Kg", "fg", "Kop", "fop", "Kx")}
+    t0 = time.time()
+    for j, c in enumerate(cfgs):
+        c = int(c)
+        assert int(cfg_ids[j]) == base + c
+        OL = _oracle_laser(O, wl["lasers"][c])
         OL.field = wl["field_order"]
-        _oracle_check_batched(O, OL, torch, arr, c, [5, n // 2 + 3, n - 2], wl["seed"], base + c,
-                              wl["r_factor"], wl["k_first"], wl["k_last"], 0,
-                              f" sweep64 batched cfg {c}")
+        Kg, fg, gtb, gx = _oracle_check_batched(O, OL, torch, B, arr, c, atoms_all[j].astype(np.int64),
+                                                wl["seed"], base + c, wl["r_factor"], wl["k_first"],
+                                                wl["k_last"], 0, f"sweep64 batched cfg {c}")
+        fin = np.isfinite(gtb)
+        Kx = Kx_all[j].ravel()
+        assert np.array_equal(np.isfinite(Kx), fin)
+        ref = O.push(OL, gtb, *gx, K)
+        Kop, _, _, fop = O.epilogue(*(r[fin] for r in ref[:3]))
+        for k, v in (("Kg", Kg), ("fg", fg), ("Kop", Kop), ("fop", fop), ("Kx", Kx[fin])):
+            pool[k].append(v)
+        mo = int((~parity.within(Kg, Kop)).sum())
+        mx = int((~parity.within(Kg, Kx[fin])).sum())
+        _log(f"sweep64 cfg {c}: {fin.sum()} electrons of {atoms_all.shape[1]} atoms; beyond 1e-8 "
+             f"of the double oracle {mo}, of the extended oracle {mx}, direction changes "
+             f"{int((fg != fop).sum())} ({time.time() - t0:.0f} s)")
+    from gpu_common import check_fp64_values
+    check_fp64_values(*(np.concatenate(pool[k]) for k in ("Kg", "fg", "Kop", "fop")),
+                      Kx=np.concatenate(pool["Kx"]),
+                      label=f" sweep64 batched, {len(cfgs)} configurations x {atoms_all.shape[1]} atoms")
 
 
 def test_mixed_vs_fp64_full_size(env):
@@ -157,26 +189,35 @@ def test_mixed_vs_fp64_full_size(env):
     frac = float((rel <= 1e-3).double().mean())
     mean_err = float(Kmx.double().mean() / K64.double().mean() - 1)
     same = float((f64 == fmx).double().mean())
-    _log(f"mixed vs FP64, {int(fin.sum())} electrons: frac(<=1e-3) {frac:.4f}, median "
-         f"{float(rel.median()):.2e}, mean energy {mean_err:.2e}, same direction {same:.5f}")
-    assert float(rel.median()) < 1e-5
-    assert frac >= 0.98
-    assert abs(mean_err) <= 1e-3
-    assert same >= 0.999
+    hist = np.histogram(np.log10(np.maximum(rel.cpu().numpy(), 1e-17)), bins=np.arange(-17, 2))[0]
+    _log(f"mixed vs FP64, {int(fin.sum())} electrons: frac(<=1e-3) {frac:.5f}, median "
+         f"{float(rel.median()):.2e}, mean energy {mean_err:.2e}, same direction {same:.6f}; "
+         f"electrons per decade of |dK|/K from 1e-17 to 10: {hist.tolist()}")
+    assert float(rel.median()) < 1e-6
+    assert frac >= 0.999
+    assert abs(mean_err) <= 1e-4
+    assert same >= 0.9999
     # the FP64 form on sampled atoms, recomputed by the oracle from the seed
+    from golden.make_extended_refs import load
     rec = wl["lasers"][0]
     OL = _oracle_laser(O, rec)
+    OL.field = wl["field_order"]
     n, K = ens.n, ens.K
-    idx = np.arange(11, n, n // 40)
+    Kx, atoms, _, _ = load("rp_ne_mixed_1m_sampled")
+    idx = atoms[0].astype(np.int64)
     xs, ys, zs, otb = _oracle_atoms(O, OL, wl["seed"], wl["cfg_id"], idx, wl["r_factor"],
                                     wl["k_first"], wl["k_last"])
     gtb = ens.tb.reshape(n, K)[torch.as_tensor(idx, device="cuda")].cpu().numpy().ravel()
     ofin = np.isfinite(otb)
     assert np.array_equal(ofin, np.isfinite(gtb))
+    T = rec["lam"] / C_LIGHT
+    assert np.all(np.abs(gtb[ofin] - otb[ofin]) <= 1e-10 * np.maximum(np.abs(otb[ofin]), T))
     sl = torch.as_tensor((idx[:, None] * K + np.arange(K)[None, :]).ravel(), device="cuda")
     Kg, fg = gpu_energy(B, torch, *(o[sl].cpu().numpy()[ofin] for o in ens.out[:3]))
-    conditioned_energy_check(O, OL, otb, xs, ys, zs, K, Kg, fg, label=" mixed-ab FP64",
-                             shift_rel=1e-13)
+    gx = [a[torch.as_tensor(idx, device="cuda")].cpu().numpy() for a in (ens.x, ens.y, ens.z)]
+    Kx = Kx[0].ravel()
+    assert np.array_equal(np.isfinite(Kx), ofin)
+    check_fp64(O, OL, Kg, fg, gtb, *gx, K, Kx=Kx[ofin], label=" mixed-ab FP64")
 
 
 def test_large_chunked_mixed_full_chunk(env):
@@ -185,9 +226,7 @@ def test_large_chunked_mixed_full_chunk(env):
     graph): every slot accounted for, births and directions as in the
     single-configuration mixed path, and the last chunk's electrons against
     the oracle's own chain."""
-    global B_
     torch, B, P, W, O = env
-    B_ = B
     wl = dict(W.LARGE_MIXED)
     wl["lasers"] = [wl["lasers"][0], wl["lasers"][-1]]
     apc = wl["chunk"]
@@ -208,20 +247,33 @@ def test_large_chunked_mixed_full_chunk(env):
     base = wl["cfg_id"] * 1000
     for c, rec in enumerate(wl["lasers"]):
         L = P.laser_of(rec, wl["field_order"])
-        (sc, st), _ = _single(B, L, wl["seed"], base + c, n, wl["k_first"], wl["k_last"],
-                              wl["r_factor"], B.RPDLA_MIXED, spec)
+        (sc, st), (sx, sy, sz, stb, sout) = _single(B, L, wl["seed"], base + c, n, wl["k_first"],
+                                                   wl["k_last"], wl["r_factor"], B.RPDLA_MIXED,
+                                                   spec)
         st = st.cpu().numpy()
         born = int(st[0] + st[1])
         l1 = int((sc - counts[c]).abs().sum())
         bwd = tal[c, 1] / max(1, tal[c, 0] + tal[c, 1])
+        # the last chunk element by element against the single-configuration
+        # mixed path (same births; separate compilations of the same float
+        # arithmetic, so energies agree to the mixed form's own rounding)
+        sl = slice(apc * K, n * K)
+        assert torch.equal(arr["t_birth"][c, :37].reshape(-1), stb[sl])
+        fin = torch.isfinite(stb[sl])
+        Kb, fb = gpu_energy(B, torch, *(arr[k][c, :37].reshape(-1)[fin] for k in ("ux", "uy", "uz")))
+        Ks, fs = gpu_energy(B, torch, *(o[sl][fin] for o in sout[:3]))
+        rel = np.abs(Kb - Ks) / Ks
         _log(f"large cfg {c} (lambda {rec['lam'] * 1e6:.1f} um, w0 {rec['w0'] * 1e6:.1f} um): "
-             f"backward fraction {bwd:.4f}; vs single path: forward {int(tal[c, 0])} vs "
-             f"{int(st[0])}, histogram L1 {l1}")
+             f"backward fraction {bwd:.4f}; whole ensemble vs single path: forward "
+             f"{int(tal[c, 0])} vs {int(st[0])}, histogram L1 {l1} of {born}; last chunk: "
+             f"{int(fin.sum())} electrons, max |dK|/K {rel.max():.1e}, direction changes "
+             f"{int((fb != fs).sum())}")
         assert st[4] == tal[c, 4] and st[5] == tal[c, 5] == 0
-        assert abs(int(tal[c, 0]) - int(st[0])) <= 0.01 * born + 2
-        assert l1 <= 0.05 * born + 4
+        assert np.all(rel <= 1e-3) and np.all(fb == fs)
+        assert abs(int(tal[c, 0]) - int(st[0])) <= allowed_failures(born) + 1
+        assert l1 <= 0.01 * born + 4
         OL = _oracle_laser(O, rec)
         OL.field = wl["field_order"]
-        _oracle_check_batched(O, OL, torch, arr, c, np.arange(37), wl["seed"], base + c,
+        _oracle_check_batched(O, OL, torch, B, arr, c, np.arange(37), wl["seed"], base + c,
                               wl["r_factor"], wl["k_first"], wl["k_last"], apc,
                               f"large batched cfg {c} last chunk", mixed=True)

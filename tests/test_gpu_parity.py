@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 import seeded_inputs as SI
-from gpu_common import BEAM, C_LIGHT, allowed_failures, energy_parity, gpu_energy, require_gpu
+from gpu_common import (BEAM, C_LIGHT, allowed_failures, check_fp64, energy_parity, gpu_energy,
+                        require_gpu)
 
 pytestmark = pytest.mark.gpu
 
@@ -137,31 +138,18 @@ def _push_case(env, order, n_atoms, prec=0, **kw):
 
 @pytest.mark.parametrize("order", [1, 5])
 def test_push_parity_fp64(env, order):
+    """FP64 push on identical seeded inputs (positions, birth times): the FP64
+    energy rule of oracle/parity.py against the double oracle's push and the
+    extended-precision build's push of the same inputs, all electrons."""
     torch, B, _ = env
-    otb, g, ref, O, OL, (xs, ys, zs) = _push_case(env, order, 100)
+    otb, g, ref, O, OL, (xs, ys, zs) = _push_case(env, order, 150)
     fin = np.isfinite(otb)
     for a in g:
         assert np.all(np.isnan(a[~fin])) and np.all(np.isfinite(a[fin]))
     Kg, fg = gpu_energy(B, torch, *(a[fin] for a in g[:3]))
-    Ko, _, _, fo = O.epilogue(*(r[fin] for r in ref[:3]))
-    ok, same_dir = energy_parity(Kg, fg, Ko, fo)
-    nb = fin.sum()
-    assert nb > 600
-    # conditioning: the oracle's own change when its birth times move by a
-    # few ulp; where that alone exceeds 1e-10, 1e-8 agreement is not
-    # determined by FP64 and the bar is the oracle's own spread
-    T = BEAM["lam"] / C_LIGHT
-    pert = O.push(OL, otb + np.where(fin, 1e-15 * np.maximum(np.abs(otb), T), 0.0), xs, ys, zs, 8)
-    Kp = O.epilogue(*(r[fin] for r in pert[:3]))[0]
-    kappa = np.abs(Kp - Ko) / Ko
-    rel = np.abs(Kg - Ko) / Ko
-    well = kappa < 1e-10
-    print(f"push parity order {order}: {ok.mean():.4f} within 1e-8, {well.sum()} of {nb} "
-          f"well-conditioned, max relative difference {rel.max():.1e}")
-    assert (~ok[well]).sum() <= allowed_failures(well.sum()), np.sort(rel[well])[-5:]
-    assert np.all(rel[~well] <= np.maximum(1e-8, 1e3 * kappa[~well]))
-    assert (~ok).sum() <= max(2, nb // 200)
-    assert (~same_dir).sum() <= allowed_failures(nb) + 1
+    assert fin.sum() >= 1000
+    check_fp64(O, OL, Kg, fg, otb, xs, ys, zs, 8, extended_push=True,
+               label=f" push order {order}")
     assert Kg.max() > 1.0    # MeV-scale acceleration happens
     # final positions
     for a, r in zip(g[3:], ref[3:]):
@@ -231,10 +219,37 @@ def test_mixed_vs_fp64(env):
     rel = np.abs(Kb - Ka) / Ka
     frac = np.mean(rel <= 1e-3)
     print(f"mixed: frac(|dK|/K <= 1e-3) = {frac:.4f}, mean dK/K = {Kb.mean() / Ka.mean() - 1:.2e}")
-    assert np.median(rel) < 1e-5
+    # measured on this beam (1e21 W/cm^2, w0 3 um): 98.6% within 1e-3; the
+    # rest are trajectories whose energy amplifies rounding (see DESIGN)
+    assert np.median(rel) < 1e-6
     assert frac >= 0.98, frac
     assert abs(Kb.mean() / Ka.mean() - 1) <= 1e-3
-    assert np.mean(fa == fb) >= 0.99
+    assert np.mean(fa == fb) >= 0.999
+
+
+def test_mixed_vs_oracle(env):
+    """The single-configuration mixed push against the double oracle's push of
+    the same seeded inputs, electron by electron: |dK|/K <= 1e-3 for >= 98%
+    of the electrons (the target of the mixed form; the rest amplify float
+    rounding), median below 1e-6, the ensemble-mean energy within 0.1%, the
+    same direction for >= 99.9%."""
+    torch, B, O = env
+    otb, g, ref, O, OL, _ = _push_case(env, 5, 150, prec=1)
+    fin = np.isfinite(otb)
+    for a in g:
+        assert np.all(np.isnan(a[~fin])) and np.all(np.isfinite(a[fin]))
+    Kg, fg = gpu_energy(B, torch, *(a[fin] for a in g[:3]))
+    Ko, _, _, fo = O.epilogue(*(r[fin] for r in ref[:3]))
+    rel = np.abs(Kg - Ko) / Ko
+    mean_err = Kg.mean() / Ko.mean() - 1
+    hist = np.histogram(np.log10(np.maximum(rel, 1e-17)), bins=np.arange(-17, 2))[0]
+    print(f"mixed vs oracle: {fin.sum()} electrons, within 1e-3 {np.mean(rel <= 1e-3):.4f}, "
+          f"median {np.median(rel):.1e}, mean energy {mean_err:.1e}, direction changes "
+          f"{(fg != fo).sum()}; electrons per decade of |dK|/K from 1e-17: {hist.tolist()}")
+    assert np.mean(rel <= 1e-3) >= 0.98
+    assert np.median(rel) < 1e-6
+    assert abs(mean_err) <= 1e-3
+    assert (fg != fo).sum() <= allowed_failures(fin.sum()) + 1
 
 
 def test_autotune_and_shape_independence(env):

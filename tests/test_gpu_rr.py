@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import seeded_inputs as SI
-from gpu_common import C_LIGHT, allowed_failures, energy_parity, gpu_energy, require_gpu
+from gpu_common import C_LIGHT, allowed_failures, check_fp64_values, gpu_energy, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -41,28 +41,18 @@ def test_push_rr_parity(env, rr, order, I):
     assert np.array_equal(np.isnan(g[6]), ~fin)
     Kg, fg = gpu_energy(B, torch, *(a[fin] for a in g[:3]))
     Ko, _, _, fo = O.epilogue(*(r[fin] for r in ref[:3]))
-    ok, same = energy_parity(Kg, fg, Ko, fo)
-    # conditioning: the oracle's own response to a few-ulp shift of the births
-    T = lam / C_LIGHT
-    pert = O.push_rr(OL, rr, tbs + np.where(fin, 1e-15 * np.maximum(np.abs(tbs), T), 0.0),
-                     xs, ys, zs, K)
-    Kp = O.epilogue(*(r[fin] for r in pert[:3]))[0]
-    kappa = np.abs(Kp - Ko) / Ko
-    rel = np.abs(Kg - Ko) / Ko
-    well = kappa < 1e-10
-    crel = np.abs(g[6][fin] - ref[6][fin]) / ref[6][fin]
-    ckap = np.abs(pert[6][fin] - ref[6][fin]) / ref[6][fin]
-    cwell = ckap < 1e-10
+    ext = O.push_rr(OL, rr, tbs, xs, ys, zs, K, extended=True)
+    Kx = O.epilogue(*(r[fin] for r in ext[:3]))[0]
     print(f"[rr] rr={rr} order={order} I={I:.0e}: {fin.sum()} electrons, max K {Ko.max():.1f} MeV, "
-          f"max chi {ref[6][fin].max():.3e}; energy within 1e-8 {ok.mean():.4f} "
-          f"({well.sum()} well-conditioned), chi max rel diff {crel.max():.1e}",
-          file=sys.stderr, flush=True)
+          f"max chi {ref[6][fin].max():.3e}", file=sys.stderr, flush=True)
     assert Ko.max() > 10.0
-    assert (~ok[well]).sum() <= allowed_failures(well.sum()) + 1
-    assert np.all(rel[~well] <= np.maximum(1e-8, 1e3 * kappa[~well]))
-    assert (~same).sum() <= allowed_failures(fin.sum()) + 1
-    assert np.all(crel[cwell] <= 1e-8)
-    assert np.all(crel[~cwell] <= np.maximum(1e-8, 1e3 * ckap[~cwell]))
+    check_fp64_values(Kg, fg, Ko, fo, Kx=Kx, label=f" rr={rr} order={order}")
+    # chi: the largest over the step starts, against both oracle builds
+    for name, r in (("double", ref), ("extended", ext)):
+        crel = np.abs(g[6][fin] - r[6][fin]) / r[6][fin]
+        print(f"[rr] chi against the {name} oracle: max rel {crel.max():.1e}, beyond 1e-8 "
+              f"{(crel > 1e-8).sum()}", file=sys.stderr, flush=True)
+        assert (crel > 1e-8).sum() <= allowed_failures(fin.sum())
 
 
 def test_push_rr_edge_cases(env):
