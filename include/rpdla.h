@@ -55,12 +55,21 @@ typedef enum {
 /* Field model.  RP_O1/O3/O5: radially polarized TM01 focus truncated at
  * order 1, 3, 5 of the series in eps = w0/z_r (order 1 is Eqs. (1)-(2) of
  * Sec. 2.1 with the Maxwell-consistent Ez sign; orders 3 and 5 are the
- * non-paraxial corrections the same section names).  The rest are test
- * models: PLANE_LP, Ex = A env cos(omega t - k z + phi0), By = Ex/c;
- * UNIFORM_EB, static fields test_E, test_B. */
+ * non-paraxial corrections the same section names).  LP_O1/O3/O5: the
+ * linearly polarized focus of Sec. 2.2's comparison (Fig. 4), polarized along
+ * x: the same Lax series psi = psi0 + eps^2 psi2 + eps^4 psi4 (truncated
+ * after psi0, psi2, psi4) under the vector potential x^ (i A/omega) psi
+ * e^{i(omega t - k z + phi0)}, fields from E = -grad phi - dA/dt (Lorenz
+ * gauge) and B = curl A, times the same envelope; A is the peak field at the
+ * focus, so the amplitude from intensity gives peak intensity I.  Double
+ * precision forms only (RPDLA_EUNSUPPORTED for the mixed push and for
+ * rpdla_birth_phase).  The rest are test models: PLANE_LP,
+ * Ex = A env cos(omega t - k z + phi0), By = Ex/c; UNIFORM_EB, static fields
+ * test_E, test_B. */
 typedef enum {
     RPDLA_RP_O1 = 1, RPDLA_RP_O3 = 3, RPDLA_RP_O5 = 5,
-    RPDLA_PLANE_LP = 10, RPDLA_UNIFORM_EB = 11
+    RPDLA_PLANE_LP = 10, RPDLA_UNIFORM_EB = 11,
+    RPDLA_LP_O1 = 21, RPDLA_LP_O3 = 23, RPDLA_LP_O5 = 25
 } rpdla_field;
 
 typedef enum { RPDLA_FP64 = 0, RPDLA_MIXED = 1 } rpdla_precision;
@@ -334,11 +343,12 @@ rpdla_status rpdla_histogram2d(int64_t n, const double* a, const double* b, cons
  * at a time (its constants copied from an LDS table into scalar registers)
  * and moves to another with work left when its own runs dry; lanes are
  * refilled as their electron finishes.
- * On a non-null stream that is not being captured, with more than one chunk,
- * the chunk's launch sequence is captured once in a hipGraph (the chunk index
- * advances in device memory) and replayed per chunk; graphs are cached per
+ * On a non-null stream that is not being captured, the chunk's launch
+ * sequence is captured once in a hipGraph (the chunk index advances in device
+ * memory) and replayed per chunk, one chunk included; graphs are cached per
  * argument set for the process lifetime (up to 32; further argument sets are
- * enqueued directly).  Otherwise the launches are enqueued directly.
+ * enqueued directly).  On the null stream or a capturing stream the launches
+ * are enqueued directly.
  * counts: device uint64[n_cfg][2][nE][nA], tallies: device uint64[n_cfg][6],
  * accumulated; electron_steps: device uint64[n_cfg] (accumulated) receiving
  * the number of RK4 steps taken per configuration, or NULL.  The chunk's
@@ -364,6 +374,10 @@ size_t rpdla_batched_workspace_bytes(int32_t n_cfg, int64_t atoms_per_chunk, int
 #define RPDLA_WS_NARRAYS 7
 rpdla_status rpdla_batched_workspace_layout(int32_t n_cfg, int64_t atoms_per_chunk,
                                            int32_t k_first, int32_t k_last, size_t* offsets);
+/* Number of chunk graphs the library holds (captured by rpdla_run_batched,
+ * kept until the process ends, at most 32).  Host only, no device work. */
+int32_t rpdla_batched_graphs(void);
+
 rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t seed,
                                uint32_t cfg_base, int64_t atoms_per_cfg, int64_t atoms_per_chunk,
                                double r_factor, int32_t k_first, int32_t k_last,

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "librpdla.so")
 
 RPDLA_OK, RPDLA_EINVAL, RPDLA_ERANGE, RPDLA_EHIP, RPDLA_ENOMEM, RPDLA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RPDLA_RP_O1, RPDLA_RP_O3, RPDLA_RP_O5, RPDLA_PLANE_LP, RPDLA_UNIFORM_EB = 1, 3, 5, 10, 11
+RPDLA_LP_O1, RPDLA_LP_O3, RPDLA_LP_O5 = 21, 23, 25
 RPDLA_FP64, RPDLA_MIXED = 0, 1
 RPDLA_WIN_ARRIVAL, RPDLA_WIN_LAB = 0, 1
 RPDLA_ANG_POLAR, RPDLA_ANG_AZIMUTH = 0, 1
@@ -99,6 +100,7 @@ def _load():
         "rpdla_histogram": (i32, [i64, vp, vp, vp, vp, HP, vp, vp, vp]),
         "rpdla_epilogue": (i32, [i64, vp, vp, vp, vp, vp, vp, vp, vp]),
         "rpdla_batched_workspace_bytes": (C.c_size_t, [i32, i64, i32, i32]),
+        "rpdla_batched_graphs": (i32, []),
         "rpdla_run_batched": (i32, [LP, i32, u64, u32, i64, i64, d, i32, i32, i32, HP, vp, vp,
                                     vp, vp, C.c_size_t, vp]),
         "rpdla_autotune": (i32, [LP, i32, i64, i32, i32, C.c_char_p, C.c_size_t, vp]),
@@ -375,6 +377,12 @@ def rpdla_kernel_occupancy(kernel, field, precision) -> dict:
 
 def rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last) -> int:
     return int(lib.rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last))
+
+
+def rpdla_batched_graphs() -> int:
+    """Chunk graphs held by the library (rpdla_run_batched on a side stream
+    captures one per argument set)."""
+    return int(lib.rpdla_batched_graphs())
 
 
 RPDLA_WS_NARRAYS = 7

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "rpdla_api.hip")
 HEADERS = [os.path.join(PKG, "csrc", f) for f in
            ("rpdla_device.hpp", "rpdla_kernels.hpp", "rpdla_batched.hpp", "rpdla_fastmath.hpp",
-            "rpdla_fastmath_coeffs.hpp")] + \
+            "rpdla_fastmath_coeffs.hpp", "rpdla_lp_coeffs.hpp")] + \
           [os.path.join(ROOT, "include", "rpdla.h")]
 LIB = os.path.join(PKG, "librpdla.so")
 ARCH = os.environ.get("RPDLA_OFFLOAD_ARCH", "gfx950")

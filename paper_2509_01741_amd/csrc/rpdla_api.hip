@@ -74,6 +74,9 @@ rpdla_status fail(rpdla_status s, const char* fmt, ...)
 
 bool is_fin(double v) { return isfinite(v) != 0; }
 
+// Linearly polarized focus (orders 1, 3, 5): double-precision forms only.
+bool is_lp(int field) { return field == RPDLA_LP_O1 || field == RPDLA_LP_O3 || field == RPDLA_LP_O5; }
+
 rpdla_status check_laser(const rpdla_laser* L)
 {
     if (!L) return fail(RPDLA_EINVAL, "laser is NULL");
@@ -88,7 +91,7 @@ rpdla_status check_laser(const rpdla_laser* L)
         return fail(RPDLA_EINVAL, "phi0 and the field scales must be finite");
     const int f = L->field;
     if (!(f == RPDLA_RP_O1 || f == RPDLA_RP_O3 || f == RPDLA_RP_O5 || f == RPDLA_PLANE_LP ||
-          f == RPDLA_UNIFORM_EB))
+          f == RPDLA_UNIFORM_EB || is_lp(f)))
         return fail(RPDLA_EINVAL, "unknown field model %d", f);
     if (!(L->window == RPDLA_WIN_ARRIVAL || L->window == RPDLA_WIN_LAB))
         return fail(RPDLA_EINVAL, "unknown window %d", L->window);
@@ -140,6 +143,7 @@ DevCfg make_cfg(const rpdla_laser* L)
     c.tb_n = om * L->t_before;
     c.ta_n = om * L->t_after;
     c.er_scale = L->er_scale; c.ez_scale = L->ez_scale;
+    c.er_w = c.er_scale * c.inv_w0n; c.ez_e = c.ez_scale * c.eps;
     for (int i = 0; i < 3; ++i) {
         c.tE[i] = kQe * L->test_E[i] / (kMe * kC * om);
         c.tB[i] = kQe * L->test_B[i] / (kMe * om);
@@ -238,10 +242,12 @@ rpdla_status launch_push(const DevCfg& c, int prec, const rpdla::PushIO& io, hip
         auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecF64>;
         const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
         hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
-    } else {
+    } else if constexpr (FIELD < 20) {
         auto* kern = rpdla::push_kernel<FIELD, rpdla::ElecMixed>;
         const int g = persistent_blocks(kern, io.n_slots, sh.block, sh.grid_factor);
         hipLaunchKernelGGL(kern, dim3(g), dim3(sh.block), 0, st, c, io);
+    } else {
+        return fail(RPDLA_EUNSUPPORTED, "the linearly polarized focus has no mixed form");
     }
     RPDLA_HIP(hipGetLastError());
     return RPDLA_OK;
@@ -311,6 +317,9 @@ rpdla_status enqueue_push(const rpdla_laser* L, int32_t precision, int64_t n_slo
     case 3: return launch_push<3>(c, precision, io, s);
     case 5: return launch_push<5>(c, precision, io, s);
     case 10: return launch_push<10>(c, precision, io, s);
+    case 21: return launch_push<21>(c, precision, io, s);
+    case 23: return launch_push<23>(c, precision, io, s);
+    case 25: return launch_push<25>(c, precision, io, s);
     default: return launch_push<11>(c, precision, io, s);
     }
 }
@@ -437,6 +446,8 @@ rpdla_status rpdla_birth_phase(const rpdla_laser* L, int64_t n_slots, const doub
     if (slots_per_atom < 1) return fail(RPDLA_EINVAL, "slots_per_atom < 1");
     if (n_slots == 0) return RPDLA_OK;
     if (!t_birth || !x || !y || !z || !phase) return fail(RPDLA_EINVAL, "null pointer");
+    if (is_lp(L->field))
+        return fail(RPDLA_EUNSUPPORTED, "the birth phase is the radial focus's carrier phase");
     const DevCfg c = make_cfg(L);
     hipLaunchKernelGGL(rpdla::birth_phase_kernel, dim3((unsigned)cdiv(n_slots, 256)), dim3(256), 0,
                        (hipStream_t)stream, c, n_slots, t_birth, x, y, z, slots_per_atom, phase,
@@ -464,6 +475,9 @@ rpdla_status rpdla_ionize(const rpdla_laser* L, uint64_t seed, uint32_t cfg_id, 
     case 3: return launch_ionize<3>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
     case 5: return launch_ionize<5>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
     case 10: return launch_ionize<10>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
+    case 21: return launch_ionize<21>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
+    case 23: return launch_ionize<23>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
+    case 25: return launch_ionize<25>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
     default: return launch_ionize<11>(c, seed, cfg_id, first_atom, n, x, y, z, k_first, k_last, t_birth, s);
     }
 }
@@ -531,6 +545,9 @@ rpdla_status rpdla_push_rr(const rpdla_laser* L, int32_t radiation_reaction, int
     case 3: st = launch_push_rr<3>(c, rr, io, s); break;
     case 5: st = launch_push_rr<5>(c, rr, io, s); break;
     case 10: st = launch_push_rr<10>(c, rr, io, s); break;
+    case 21: st = launch_push_rr<21>(c, rr, io, s); break;
+    case 23: st = launch_push_rr<23>(c, rr, io, s); break;
+    case 25: st = launch_push_rr<25>(c, rr, io, s); break;
     default: st = launch_push_rr<11>(c, rr, io, s); break;
     }
     hipError_t fe = hipFreeAsync(q, s);
@@ -578,6 +595,9 @@ rpdla_status rpdla_push_adaptive(const rpdla_laser* L, const rpdla_adaptive* A, 
     case 3: st = launch_push_dp<3>(c, io, s); break;
     case 5: st = launch_push_dp<5>(c, io, s); break;
     case 10: st = launch_push_dp<10>(c, io, s); break;
+    case 21: st = launch_push_dp<21>(c, io, s); break;
+    case 23: st = launch_push_dp<23>(c, io, s); break;
+    case 25: st = launch_push_dp<25>(c, io, s); break;
     default: st = launch_push_dp<11>(c, io, s); break;
     }
     hipError_t fe = hipFreeAsync(q, s);
@@ -671,7 +691,7 @@ template <int FIELD, class ELEC>
 rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipStream_t s)
 {
     const size_t lds_i = (size_t)A.n_cfg * sizeof(DevCfg);
-    const size_t lds_p = (size_t)A.n_cfg * (sizeof(rpdla::PushCfg) + sizeof(unsigned long long));
+    const size_t lds_p = (size_t)A.n_cfg * sizeof(unsigned long long);
     auto* kpush = rpdla::batch_push_kernel<FIELD, ELEC>;
     auto* kion = rpdla::batch_ionize_kernel<FIELD>;
     const Shape sh = get_shape(kKindBatchPush, FIELD, std::is_same<ELEC, rpdla::ElecMixed>::value);
@@ -685,7 +705,7 @@ rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipSt
         hipLaunchKernelGGL(rpdla::batch_zero_queue_kernel, dim3(1), dim3(64), 0, st, A.ctl);
         hipLaunchKernelGGL(rpdla::batch_sample_kernel, dim3(grid_a), dim3(256), 0, st, A);
         hipLaunchKernelGGL(kion, dim3(grid_a), dim3(256), lds_i, st, A);
-        hipLaunchKernelGGL(kpush, dim3((unsigned)grid_p), dim3(sh.block), lds_p, st, A);
+        hipLaunchKernelGGL(kpush, dim3((unsigned)grid_p), dim3(sh.block), lds_p, st, A, A.cfgs);
         hipLaunchKernelGGL(rpdla::batch_hist_kernel, dim3((unsigned)grid_h), dim3(256), 0, st, A);
         hipLaunchKernelGGL(rpdla::batch_advance_kernel, dim3(1), dim3(64), 0, st, A.ctl);
         RPDLA_HIP(hipGetLastError());
@@ -694,7 +714,7 @@ rpdla_status run_batched_impl(const rpdla::BatchArgs& A, int64_t n_chunks, hipSt
 
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (s != nullptr) RPDLA_HIP(hipStreamIsCapturing(s, &cap));
-    if (s == nullptr || cap != hipStreamCaptureStatusNone || n_chunks == 1) {
+    if (s == nullptr || cap != hipStreamCaptureStatusNone) {
         for (int64_t i = 0; i < n_chunks; ++i) {
             rpdla_status r = enqueue_chunk(s);
             if (r != RPDLA_OK) return r;
@@ -764,6 +784,12 @@ rpdla_status rpdla_batched_workspace_layout(int32_t n_cfg, int64_t atoms_per_chu
     return RPDLA_OK;
 }
 
+int32_t rpdla_batched_graphs(void)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    return (int32_t)g_graphs.size();
+}
+
 rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t seed,
                                uint32_t cfg_base, int64_t atoms_per_cfg, int64_t atoms_per_chunk,
                                double r_factor, int32_t k_first, int32_t k_last, int32_t precision,
@@ -782,6 +808,8 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
     }
     if (!(precision == RPDLA_FP64 || precision == RPDLA_MIXED))
         return fail(RPDLA_EINVAL, "unknown precision %d", precision);
+    if (precision == RPDLA_MIXED && is_lp(cfgs[0].field))
+        return fail(RPDLA_EUNSUPPORTED, "the linearly polarized focus has no mixed form");
     if (!(1 <= k_first && k_first <= k_last && k_last <= 10))
         return fail(RPDLA_EINVAL, "need 1 <= k_first <= k_last <= 10");
     if (atoms_per_cfg < 0) return fail(RPDLA_EINVAL, "atoms_per_cfg < 0");
@@ -848,6 +876,9 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
                          : run_batched_impl<5, rpdla::ElecF64>(A, n_chunks, s);
     case 10: return mixed ? run_batched_impl<10, rpdla::ElecMixed>(A, n_chunks, s)
                           : run_batched_impl<10, rpdla::ElecF64>(A, n_chunks, s);
+    case 21: return run_batched_impl<21, rpdla::ElecF64>(A, n_chunks, s);
+    case 23: return run_batched_impl<23, rpdla::ElecF64>(A, n_chunks, s);
+    case 25: return run_batched_impl<25, rpdla::ElecF64>(A, n_chunks, s);
     default: return mixed ? run_batched_impl<11, rpdla::ElecMixed>(A, n_chunks, s)
                           : run_batched_impl<11, rpdla::ElecF64>(A, n_chunks, s);
     }
@@ -1080,12 +1111,20 @@ rpdla_status field_kernel_info(int kind, bool mixed, int32_t* v, int32_t* s, dou
     const Shape sh = get_shape(kind, FIELD, kind == kKindIonize ? 0 : (mixed ? 1 : 0));
     if (kind == kKindIonize)
         return kernel_info(rpdla::ionize_kernel<FIELD>, sh.block, 0, v, s, w);
+    if constexpr (FIELD > 20) {
+        if (mixed) return fail(RPDLA_EUNSUPPORTED, "the linearly polarized focus has no mixed form");
+        const size_t lds = (size_t)rpdla::kMaxCfg * sizeof(unsigned long long);
+        return kind == kKindPush
+                   ? kernel_info(rpdla::push_kernel<FIELD, rpdla::ElecF64>, sh.block, 0, v, s, w)
+                   : kernel_info(rpdla::batch_push_kernel<FIELD, rpdla::ElecF64>, sh.block, lds, v, s, w);
+    } else {
     if (kind == kKindPush)
         return mixed ? kernel_info(rpdla::push_kernel<FIELD, rpdla::ElecMixed>, sh.block, 0, v, s, w)
                      : kernel_info(rpdla::push_kernel<FIELD, rpdla::ElecF64>, sh.block, 0, v, s, w);
-    const size_t lds = (size_t)rpdla::kMaxCfg * (sizeof(rpdla::PushCfg) + sizeof(unsigned long long));
+    const size_t lds = (size_t)rpdla::kMaxCfg * sizeof(unsigned long long);
     return mixed ? kernel_info(rpdla::batch_push_kernel<FIELD, rpdla::ElecMixed>, sh.block, lds, v, s, w)
                  : kernel_info(rpdla::batch_push_kernel<FIELD, rpdla::ElecF64>, sh.block, lds, v, s, w);
+    }
 }
 
 }  // namespace
@@ -1105,6 +1144,9 @@ rpdla_status rpdla_kernel_occupancy(int32_t kernel, int32_t field, int32_t preci
     case 5: return field_kernel_info<5>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
     case 10: return field_kernel_info<10>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
     case 11: return field_kernel_info<11>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
+    case 21: return field_kernel_info<21>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
+    case 23: return field_kernel_info<23>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
+    case 25: return field_kernel_info<25>(kernel, mixed, vgprs, scratch_bytes, waves_per_simd);
     default: return fail(RPDLA_EINVAL, "unknown field model %d", field);
     }
 }

@@ -104,49 +104,32 @@ __global__ void __launch_bounds__(256, 2) batch_ionize_kernel(BatchArgs A)
                        A.y[i] * cf.k, A.z[i] * cf.k, A.k_first, A.K, A.tb + i * A.K);
 }
 
-// Copy a wave-uniform record (same address in every lane) into scalar
-// registers: every 32-bit word goes through readfirstlane.
-template <class T>
-__device__ inline T uniform_copy(const T* p)
-{
-    static_assert(sizeof(T) % 4 == 0, "record must be a whole number of words");
-    T out;
-    const int* src = reinterpret_cast<const int*>(p);
-    int* dst = reinterpret_cast<int*>(&out);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
-    return out;
-}
-
 // One persistent launch over n_cfg * apc * K slots.  Slot j belongs to
 // configuration j / (apc K) and atom (j / K) % apc of the chunk.  Every
 // configuration has its own work counter, and a wave works on ONE
 // configuration at a time: it starts on configuration (wave id mod n_cfg),
 // refills its lanes from that configuration's counter, and when the counter
 // is exhausted lets its lanes finish and moves on to the next configuration
-// that still has work.  The wave's configuration is therefore uniform: its
-// constants are copied from the LDS table into scalar registers once per
-// switch, and the step's vector registers hold electron state only.  Final
+// that still has work.  The wave's configuration index is therefore uniform,
+// and its constants are read from the configuration table (a separate
+// read-only kernel argument) with scalar loads at a uniform address, so they
+// never occupy vector registers and the compiler can reload instead of
+// spilling them.  The step's vector registers hold electron state only.  Final
 // momenta go to the chunk's u arrays (NaN for invalid births; unborn and
 // inactive slots are not written).
 template <int FIELD, class ELEC>
-__global__ void __launch_bounds__(256, ElecWaves<ELEC>::value) batch_push_kernel(BatchArgs A)
+__global__ void __launch_bounds__(256, ElecWaves<ELEC>::value) batch_push_kernel(
+    BatchArgs A, const DevCfg* __restrict__ cfgs)
 {
-    extern __shared__ double lds_raw[];
+    extern __shared__ unsigned long long s_steps[];   // [n_cfg] steps taken in this block
     const int ncfg = A.n_cfg;
-    PushCfg* s_pc = reinterpret_cast<PushCfg*>(lds_raw);
-    unsigned long long* s_steps = reinterpret_cast<unsigned long long*>(s_pc + ncfg);
-    for (int w = threadIdx.x; w < ncfg; w += blockDim.x) {
-        s_pc[w] = push_cfg_of(A.cfgs[w]);
-        s_steps[w] = 0ull;
-    }
+    for (int w = threadIdx.x; w < ncfg; w += blockDim.x) s_steps[w] = 0ull;
     __syncthreads();
 
     const int64_t per_cfg = A.apc * A.K;
     const int64_t first = (int64_t)A.ctl->chunk * A.apc;
     const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     int cw = __builtin_amdgcn_readfirstlane(wave % ncfg);
-    PushCfg uc = uniform_copy(&s_pc[cw]);
     int64_t idx = -1;
     bool draining = false;
     ELEC e;
@@ -167,9 +150,15 @@ __global__ void __launch_bounds__(256, ElecWaves<ELEC>::value) batch_push_kernel
                         const double t0 = A.tb[js];
                         if (first + a < A.atoms_per_cfg && t0 < __builtin_inf()) {
                             const int64_t ia = (int64_t)cw * A.apc + a;
-                            if (elec_init(uc, e, t0, A.x[ia], A.y[ia], A.z[ia])) {
-                                idx = js;
-                                if (e.N > 0) atomicAdd(&s_steps[cw], (unsigned long long)e.N);
+                            if (elec_init(cfgs[cw], e, t0, A.x[ia], A.y[ia], A.z[ia])) {
+                                if (e.N > 0) {
+                                    idx = js;
+                                    atomicAdd(&s_steps[cw], (unsigned long long)e.N);
+                                } else {
+                                    double ux, uy, uz, xf, yf, zf;
+                                    elec_final(cfgs[cw], e, ux, uy, uz, xf, yf, zf);
+                                    A.ux[js] = ux; A.uy[js] = uy; A.uz[js] = uz;
+                                }
                             } else {
                                 const double q = __builtin_nan("");
                                 A.ux[js] = q; A.uy[js] = q; A.uz[js] = q;
@@ -191,16 +180,17 @@ __global__ void __launch_bounds__(256, ElecWaves<ELEC>::value) batch_push_kernel
             }
             if (next < 0) break;
             cw = __builtin_amdgcn_readfirstlane(next);
-            uc = uniform_copy(&s_pc[cw]);
             draining = false;
             continue;
         }
-        if ((idx >= 0) && (e.n < e.N)) elec_step<FIELD>(uc, e);
-        if ((idx >= 0) && (e.n >= e.N)) {
-            double ux, uy, uz, xf, yf, zf;
-            elec_final(uc, e, ux, uy, uz, xf, yf, zf);
-            A.ux[idx] = ux; A.uy[idx] = uy; A.uz[idx] = uz;
-            idx = -1;
+        if (idx >= 0) {
+            elec_step<FIELD>(cfgs[cw], e);
+            if (e.n == e.N) {
+                double ux, uy, uz, xf, yf, zf;
+                elec_final(cfgs[cw], e, ux, uy, uz, xf, yf, zf);
+                A.ux[idx] = ux; A.uy[idx] = uy; A.uz[idx] = uz;
+                idx = -1;
+            }
         }
     }
     if (A.steps) {

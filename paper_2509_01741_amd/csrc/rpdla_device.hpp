@@ -12,13 +12,15 @@
 #include <stdint.h>
 
 #include "rpdla_fastmath.hpp"
+#include "rpdla_lp_coeffs.hpp"
 
 namespace rpdla {
 
 constexpr int kMaxStates = 10;
 
 // Per-configuration constants, built on the host (rpdla_api.hip) and passed
-// by value to kernels or staged in LDS by the batched kernel.
+// by value to kernels, staged in LDS by the batched ionization kernel and read
+// with scalar loads by the batched push.
 struct DevCfg {
     double omega, inv_omega;     // carrier angular frequency [rad/s]
     double k, inv_k;             // wavenumber [1/m]
@@ -32,6 +34,7 @@ struct DevCfg {
     double hn;                   // omega dt
     double tb_n, ta_n;           // omega t_before, omega t_after
     double er_scale, ez_scale;
+    double er_w, ez_e;           // er_scale/(k w0) and ez_scale eps (folded products)
     double tE[3], tB[3];         // normalized uniform test fields
     int32_t field, window;
     // tunnelling rate per normalized time for state k (index k-1):
@@ -47,26 +50,6 @@ struct DevCfg {
     double ad_rtol, ad_atol, ad_hmax, ad_ktol;
     int64_t ad_max_steps;
 };
-
-// The subset of DevCfg the push needs (staged in LDS by the batched push).
-struct PushCfg {
-    double omega, k, inv_k, a0, inv_w0n2, inv_w0n, inv_zrn;
-    double eps, e2, e3, e4, inv_T0n, phi0, hn, tb_n, ta_n, er_scale, ez_scale;
-    double tE[3], tB[3];
-    int32_t field, window;
-};
-
-__host__ __device__ inline PushCfg push_cfg_of(const DevCfg& c)
-{
-    PushCfg p;
-    p.omega = c.omega; p.k = c.k; p.inv_k = c.inv_k; p.a0 = c.a0; p.inv_w0n2 = c.inv_w0n2;
-    p.inv_w0n = c.inv_w0n; p.inv_zrn = c.inv_zrn; p.eps = c.eps; p.e2 = c.e2; p.e3 = c.e3;
-    p.e4 = c.e4; p.inv_T0n = c.inv_T0n; p.phi0 = c.phi0; p.hn = c.hn; p.tb_n = c.tb_n; p.ta_n = c.ta_n;
-    p.er_scale = c.er_scale; p.ez_scale = c.ez_scale;
-    for (int i = 0; i < 3; ++i) { p.tE[i] = c.tE[i]; p.tB[i] = c.tB[i]; }
-    p.field = c.field; p.window = c.window;
-    return p;
-}
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -109,9 +92,9 @@ __device__ inline double uniform_j(uint64_t seed, uint32_t cfg, uint64_t atom, i
 // rho = r/w0, zeta = z/z_r, D = 1 + zeta^2, q = (1 + i zeta)/D,
 // Psi = phi0 + tau - Z - rho^2 zeta/D and g = a0 exp(-rho^2/D - s^2),
 // s = (tau - Z)/(omega tau0), the complex amplitudes Q_n = g e^{i Psi} q^n
-// (C_n = Re Q_n, S_n = Im Q_n) come from repeated complex multiplication by q
-// -- one sine/cosine and one exponential per evaluation, the Gouy phase
-// carried by q.  Then
+// (C_n = Re Q_n, S_n = Im Q_n) carry the Gouy phase in the powers of q, so an
+// evaluation needs one sine/cosine and one exponential (below the powers are
+// formed by repeated multiplication by w = D q).  Then
 //   Er/r  = [C2 + e2(-C3/2 + rho^2 C4 - rho^4 C5/4)
 //            + e4(-3C4/8 - 3rho^2 C5/8 + 17rho^4 C6/16 - 3rho^6 C7/8 + rho^8 C8/32)] / w0
 //   Ez    = eps(S2 - rho^2 S3) + e3(S3/2 + rho^2 S4/2 - 5rho^4 S5/4 + rho^6 S6/4)
@@ -130,79 +113,93 @@ __device__ inline Cx<T> cmul(Cx<T> a, Cx<T> b)
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 
-// Transverse / longitudinal factors shared by the double and mixed paths.
-// Inputs: Q[n] for n = 2..8 (only the orders needed are read), r2 = rho^2.
+// The same series arranged for fewer operations (double and float).  With
+// w = 1 + i zeta (so q = iD w), write Q_n = iD^(n-2) R_n, R_n = G w^n,
+// G = g iD^2 e^{i Psi}: one multiplication by w is two fused multiply-adds.
+// The powers of iD then pair with those of rho^2 into rD = rho^2 iD and with
+// e2 into E = e2 iD, so each bracket is a polynomial in rD (Horner) and
+//   PE = Re{R2 + E (-R3/2 + rD R4 - rD^2 R5/4)
+//          + E^2 (-3R4/8 - 3rD R5/8 + 17rD^2 R6/16 - 3rD^3 R7/8 + rD^4 R8/32)}
+//   PB = Re{R2 + E (R3/2 + rD R4/2 - rD^2 R5/4)
+//          + E^2 (3R4/8 + 3rD R5/8 + 3rD^2 R6/16 - rD^3 R7/4 + rD^4 R8/32)}
+//   EZ = eps Im{R2 - rD R3 + E (R3/2 + rD R4/2 - 5rD^2 R5/4 + rD^3 R6/4)}
+// (E^2 = e4 iD^2 and eps E = e3 iD: the terms of the series above, term by
+// term).
 template <int ORDER, typename T>
-__device__ inline void rp_combine(const Cx<T>* Q, T r2, T eps, T e2, T e3, T e4,
-                                  T& PE, T& PB, T& EZ)
+__device__ inline void rp_brackets(T G_re, T G_im, T zeta, T rD, T E, T& PE, T& PB, T& EZe)
 {
-    const T C2 = Q[2].re, S2 = Q[2].im, C3 = Q[3].re, S3 = Q[3].im;
-    PE = C2;
-    PB = C2;
-    EZ = eps * (S2 - r2 * S3);
+    constexpr int NMAX = ORDER >= 5 ? 8 : ORDER >= 3 ? 6 : 3;
+    T Rr[NMAX + 1], Ri[NMAX + 1];
+    Rr[0] = G_re;
+    Ri[0] = G_im;
+#pragma unroll
+    for (int n = 1; n <= NMAX; ++n) {
+        Rr[n] = fma(-zeta, Ri[n - 1], Rr[n - 1]);
+        Ri[n] = fma(zeta, Rr[n - 1], Ri[n - 1]);
+    }
+    PE = Rr[2];
+    PB = Rr[2];
+    EZe = fma(-rD, Ri[3], Ri[2]);
     if constexpr (ORDER >= 3) {
-        const T C4 = Q[4].re, S4 = Q[4].im, C5 = Q[5].re, S5 = Q[5].im, S6 = Q[6].im;
-        const T r4 = r2 * r2, r6 = r4 * r2;
-        const T h = T(0.5), q = T(0.25);
-        PE += e2 * (-h * C3 + r2 * C4 - q * r4 * C5);
-        PB += e2 * (h * C3 + h * r2 * C4 - q * r4 * C5);
-        EZ += e3 * (h * S3 + h * r2 * S4 - T(1.25) * r4 * S5 + q * r6 * S6);
+        const T h3 = T(0.5) * Rr[3], q5 = T(0.25) * Rr[5];
+        const T pe2 = fma(fma(-q5, rD, Rr[4]), rD, -h3);
+        const T pb2 = fma(fma(-q5, rD, T(0.5) * Rr[4]), rD, h3);
+        const T ez3 = fma(fma(fma(T(0.25) * Ri[6], rD, T(-1.25) * Ri[5]), rD, T(0.5) * Ri[4]), rD,
+                          T(0.5) * Ri[3]);
+        EZe = fma(E, ez3, EZe);
         if constexpr (ORDER >= 5) {
-            const T C6 = Q[6].re, C7 = Q[7].re, C8 = Q[8].re;
-            const T r8 = r4 * r4;
-            const T c38 = T(0.375), c132 = T(0.03125);
-            PE += e4 * (-c38 * C4 - c38 * r2 * C5 + T(1.0625) * r4 * C6 - c38 * r6 * C7
-                        + c132 * r8 * C8);
-            PB += e4 * (c38 * C4 + c38 * r2 * C5 + T(0.1875) * r4 * C6 - q * r6 * C7
-                        + c132 * r8 * C8);
+            const T t8 = T(0.03125) * Rr[8], t5 = T(0.375) * Rr[5], t4 = T(0.375) * Rr[4];
+            const T pe4 = fma(fma(fma(fma(t8, rD, T(-0.375) * Rr[7]), rD, T(1.0625) * Rr[6]), rD, -t5),
+                              rD, -t4);
+            const T pb4 = fma(fma(fma(fma(t8, rD, T(-0.25) * Rr[7]), rD, T(0.1875) * Rr[6]), rD, t5),
+                              rD, t4);
+            PE = fma(E, fma(E, pe4, pe2), PE);
+            PB = fma(E, fma(E, pb4, pb2), PB);
+        } else {
+            PE = fma(E, pe2, PE);
+            PB = fma(E, pb2, PB);
         }
     }
 }
 
-// Complex amplitudes Q_2..Q_NMAX from the carrier (cs, sn), amplitude g, and q.
-template <int ORDER, typename T>
-__device__ inline void rp_amplitudes(T g, T cs, T sn, Cx<T> q, Cx<T>* Q)
-{
-    const Cx<T> q2 = cmul(q, q);
-    Q[2] = cmul(Cx<T>{g * cs, g * sn}, q2);
-    Q[3] = cmul(Q[2], q);
-    if constexpr (ORDER >= 3) {
-        Q[4] = cmul(Q[3], q);
-        Q[5] = cmul(Q[4], q);
-        Q[6] = cmul(Q[5], q);
-        if constexpr (ORDER >= 5) {
-            Q[7] = cmul(Q[6], q);
-            Q[8] = cmul(Q[7], q);
-        }
-    }
-}
-
-// Double-precision field at normalized (X, Y, Z, tau).  WANT_B = false skips
-// the magnetic field (ionization needs |E| only).
-template <int ORDER, bool WANT_B, class CFG>
-__device__ inline void rp_field_f64(const CFG& c, double X, double Y, double Z, double tau,
-                                    double& ax, double& ay, double& az, double& bx, double& by)
+// Double-precision radial field at normalized position (X, Y, Z) and retarded
+// time d = tau - Z (every field model depends on time only through d), in
+// the parts the force needs: a = (pe X, pe Y, az), b = (-pb Y, pb X, 0).
+// With LO the retarded time is the unevaluated sum d + dl (dl small): the
+// carrier phase goes to the sine/cosine as the pair (d, phi0 + dl - rD zeta),
+// so it is not rounded to a multiple of ulp(d).
+template <int ORDER, bool LO, class CFG>
+__device__ inline void rp_field_parts_f64(const CFG& c, double X, double Y, double Z, double d,
+                                          double dl, double& pe, double& pb, double& az)
 {
     const double r2 = (X * X + Y * Y) * c.inv_w0n2;
     const double zeta = Z * c.inv_zrn;
     const double iD = fm::rcp_f64(1.0 + zeta * zeta);
     const double rD = r2 * iD;
-    const double d = tau - Z;
-    const double Psi = c.phi0 + d - rD * zeta;
-    const double s = d * c.inv_T0n;
-    const double g = c.a0 * fm::exp_f64(-rD - s * s);
+    const double psi_lo = fma(-rD, zeta, LO ? c.phi0 + dl : c.phi0);
+    const double s = (LO ? d + dl : d) * c.inv_T0n;
+    const double g = c.a0 * fm::exp_fin_f64(-rD - s * s);
     double sn, cs;
-    fm::sincos_f64(Psi, &sn, &cs);
-    Cx<double> Q[9];
-    rp_amplitudes<ORDER, double>(g, cs, sn, Cx<double>{iD, zeta * iD}, Q);
-    double PE, PB, EZ;
-    rp_combine<ORDER, double>(Q, r2, c.eps, c.e2, c.e3, c.e4, PE, PB, EZ);
-    const double pe = c.er_scale * PE * c.inv_w0n;
+    fm::sincos2_f64(d, psi_lo, &sn, &cs);
+    const double gi = g * (iD * iD);
+    double PE, PB, EZe;
+    rp_brackets<ORDER, double>(gi * cs, gi * sn, zeta, rD, c.e2 * iD, PE, PB, EZe);
+    pe = c.er_w * PE;
+    pb = PB * c.inv_w0n;
+    az = c.ez_e * EZe;
+}
+
+// The radial field in Cartesian components.  WANT_B = false skips the
+// magnetic field (ionization needs |E| only).
+template <int ORDER, bool WANT_B, bool LO, class CFG>
+__device__ inline void rp_field_f64(const CFG& c, double X, double Y, double Z, double d, double dl,
+                                    double& ax, double& ay, double& az, double& bx, double& by)
+{
+    double pe, pb;
+    rp_field_parts_f64<ORDER, LO>(c, X, Y, Z, d, dl, pe, pb, az);
     ax = pe * X;
     ay = pe * Y;
-    az = c.ez_scale * EZ;
     if constexpr (WANT_B) {
-        const double pb = PB * c.inv_w0n;
         bx = -pb * Y;
         by = pb * X;
     }
@@ -234,25 +231,186 @@ __device__ inline double rp_bound2(const CFG& c, double X, double Y, double Z)
     return et * et * r2 + ez * ez;
 }
 
-// Field of any model in double precision (test models included).
-template <int FIELD, bool WANT_B, class CFG>
-__device__ inline void field_f64(const CFG& c, double X, double Y, double Z, double tau,
-                                 double& ax, double& ay, double& az, double& bx, double& by,
-                                 double& bz)
+// ---------------------------------------------------------------------------
+// Linearly polarized focus (Sec. 2.2 compares the radial focus with a linearly
+// polarized one, Fig. 4): the same Lax series with the vector potential along
+// x (the derivation and the term tables are in gen_lp_coeffs.py).  With
+// rx = x/w0, ry = y/w0, s = rx^2 + ry^2 and Q_n = g e^{i Psi} q^n as for the
+// radial focus:
+//   a_x = Re[sum_n (AX0_n + rx^2 AXR_n) Q_n],  a_y = rx ry Re[sum_n AXR_n Q_n],
+//   a_z = rx Re[sum_n AZ_n Q_n],  b_x = 0,  b_y = Re[sum_n BY_n Q_n],
+//   b_z = eps ry Im[sum_n S_n Q_n],
+// each coefficient a polynomial in s and eps.  The sums are Horner in q.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ inline Cx<double> lp_coef(const lp::Term (&T)[N], int n, const double* sp,
+                                     const double* ep)
 {
+    double cr = 0.0, ci = 0.0;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+        if (T[t].n == n) {
+            const double w = ep[T[t].j] * sp[T[t].m];
+            if (T[t].re != 0.0) cr += T[t].re * w;
+            if (T[t].im != 0.0) ci += T[t].im * w;
+        }
+    }
+    return {cr, ci};
+}
+
+// sum_n c_n q^n over n = NMIN..NMAX (Horner, then the factor q^NMIN).
+template <int N, int NMIN, int NMAX>
+__device__ inline Cx<double> lp_sum(const lp::Term (&T)[N], const double* sp, const double* ep,
+                                    Cx<double> q)
+{
+    Cx<double> u = lp_coef(T, NMAX, sp, ep);
+#pragma unroll
+    for (int n = NMAX - 1; n >= NMIN; --n) {
+        const Cx<double> c = lp_coef(T, n, sp, ep);
+        u = cmul(u, q);
+        u.re += c.re;
+        u.im += c.im;
+    }
+#pragma unroll
+    for (int n = 0; n < NMIN; ++n) u = cmul(u, q);
+    return u;
+}
+
+// Upper bound of |sum_n c_n Q_n| / (g): sum of the coefficient magnitudes
+// times |q|^n.
+template <int N>
+__device__ inline double lp_bound_sum(const lp::Term (&T)[N], const double* sp, const double* ep,
+                                      double qabs)
+{
+    double b = 0.0;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+        double qn = 1.0;
+        for (int i = 0; i < T[t].n; ++i) qn *= qabs;
+        b += (fabs(T[t].re) + fabs(T[t].im)) * ep[T[t].j] * sp[T[t].m] * qn;
+    }
+    return b;
+}
+
+#define RPDLA_LP_SUM(ORD, NAME, sp, ep, q)                                                   \
+    lp_sum<lp::k##NAME##_O##ORD##_N, lp::k##NAME##_O##ORD##_NMIN,                            \
+           lp::k##NAME##_O##ORD##_NMAX>(lp::k##NAME##_O##ORD, sp, ep, q)
+
+template <int ORDER>
+__device__ inline void lp_sums(const double* sp, const double* ep, Cx<double> q, Cx<double>& ux0,
+                               Cx<double>& uxr, Cx<double>& uz, Cx<double>& uby, Cx<double>& us)
+{
+    if constexpr (ORDER == 1) {
+        ux0 = RPDLA_LP_SUM(1, AX0, sp, ep, q); uxr = RPDLA_LP_SUM(1, AXR, sp, ep, q);
+        uz = RPDLA_LP_SUM(1, AZ, sp, ep, q); uby = RPDLA_LP_SUM(1, BY, sp, ep, q);
+        us = RPDLA_LP_SUM(1, S, sp, ep, q);
+    } else if constexpr (ORDER == 3) {
+        ux0 = RPDLA_LP_SUM(3, AX0, sp, ep, q); uxr = RPDLA_LP_SUM(3, AXR, sp, ep, q);
+        uz = RPDLA_LP_SUM(3, AZ, sp, ep, q); uby = RPDLA_LP_SUM(3, BY, sp, ep, q);
+        us = RPDLA_LP_SUM(3, S, sp, ep, q);
+    } else {
+        ux0 = RPDLA_LP_SUM(5, AX0, sp, ep, q); uxr = RPDLA_LP_SUM(5, AXR, sp, ep, q);
+        uz = RPDLA_LP_SUM(5, AZ, sp, ep, q); uby = RPDLA_LP_SUM(5, BY, sp, ep, q);
+        us = RPDLA_LP_SUM(5, S, sp, ep, q);
+    }
+}
+
+template <class CFG>
+__device__ inline void lp_powers(const CFG& c, double s, double* sp, double* ep)
+{
+    sp[0] = 1.0; sp[1] = s; sp[2] = s * s; sp[3] = sp[2] * s; sp[4] = sp[2] * sp[2];
+    sp[5] = sp[4] * s;
+    ep[0] = 1.0; ep[1] = c.eps; ep[2] = c.e2; ep[3] = c.e3; ep[4] = c.e4; ep[5] = c.e4 * c.eps;
+    ep[6] = c.e3 * c.e3; ep[7] = ep[6] * c.eps;
+}
+
+template <int ORDER, bool WANT_B, class CFG>
+__device__ inline void lp_field_f64(const CFG& c, double X, double Y, double Z, double d,
+                                    double& ax, double& ay, double& az, double& bx, double& by,
+                                    double& bz)
+{
+    const double rx = X * c.inv_w0n, ry = Y * c.inv_w0n;
+    const double s = rx * rx + ry * ry;
+    const double zeta = Z * c.inv_zrn;
+    const double iD = fm::rcp_f64(1.0 + zeta * zeta);
+    const double Psi = c.phi0 + d - s * zeta * iD;
+    const double sg = d * c.inv_T0n;
+    const double g = c.a0 * fm::exp_fin_f64(-s * iD - sg * sg);
+    double sn, cs;
+    fm::sincos_f64(Psi, &sn, &cs);
+    const Cx<double> base{g * cs, g * sn};
+    double sp[6], ep[8];
+    lp_powers(c, s, sp, ep);
+    Cx<double> ux0, uxr, uz, uby, us;
+    lp_sums<ORDER>(sp, ep, Cx<double>{iD, zeta * iD}, ux0, uxr, uz, uby, us);
+    const Cx<double> wx0 = cmul(base, ux0), wxr = cmul(base, uxr), wz = cmul(base, uz);
+    ax = c.er_scale * (wx0.re + rx * rx * wxr.re);
+    ay = c.er_scale * rx * ry * wxr.re;
+    az = c.ez_scale * rx * wz.re;
+    bx = 0.0;
+    if constexpr (WANT_B) {
+        by = cmul(base, uby).re;
+        bz = c.eps * ry * cmul(base, us).im;
+    } else {
+        by = 0.0;
+        bz = 0.0;
+    }
+}
+
+// Spatial bound M with |a(X, tau)|^2 <= M^2 exp(-2 s^2) for the linear focus.
+template <int ORDER, class CFG>
+__device__ inline double lp_bound2(const CFG& c, double X, double Y, double Z)
+{
+    const double rx = fabs(X * c.inv_w0n), ry = fabs(Y * c.inv_w0n);
+    const double s = rx * rx + ry * ry;
+    const double zeta = Z * c.inv_zrn;
+    const double iD = 1.0 / (1.0 + zeta * zeta);
+    const double qabs = sqrt(iD);
+    const double gs = c.a0 * exp(-s * iD);
+    double sp[6], ep[8];
+    lp_powers(c, s, sp, ep);
+    double bx0, bxr, bz;
+    if constexpr (ORDER == 1) {
+        bx0 = lp_bound_sum(lp::kAX0_O1, sp, ep, qabs); bxr = lp_bound_sum(lp::kAXR_O1, sp, ep, qabs);
+        bz = lp_bound_sum(lp::kAZ_O1, sp, ep, qabs);
+    } else if constexpr (ORDER == 3) {
+        bx0 = lp_bound_sum(lp::kAX0_O3, sp, ep, qabs); bxr = lp_bound_sum(lp::kAXR_O3, sp, ep, qabs);
+        bz = lp_bound_sum(lp::kAZ_O3, sp, ep, qabs);
+    } else {
+        bx0 = lp_bound_sum(lp::kAX0_O5, sp, ep, qabs); bxr = lp_bound_sum(lp::kAXR_O5, sp, ep, qabs);
+        bz = lp_bound_sum(lp::kAZ_O5, sp, ep, qabs);
+    }
+    const double ex = fabs(c.er_scale) * gs * (bx0 + rx * rx * bxr);
+    const double ey = fabs(c.er_scale) * gs * rx * ry * bxr;
+    const double ez = fabs(c.ez_scale) * gs * rx * bz;
+    return ex * ex + ey * ey + ez * ez;
+}
+
+// Field of any model in double precision (test models included) at position
+// (X, Y, Z) and retarded time d = tau - Z; with LO the retarded time is the
+// unevaluated sum d + dl (the radial focus keeps the pair, the others add it).
+template <int FIELD, bool WANT_B, class CFG, bool LO = false>
+__device__ inline void field_f64(const CFG& c, double X, double Y, double Z, double d,
+                                 double& ax, double& ay, double& az, double& bx, double& by,
+                                 double& bz, double dl = 0.0)
+{
+    if constexpr (LO && !(FIELD == 1 || FIELD == 3 || FIELD == 5)) {
+        d += dl;
+    }
     if constexpr (FIELD == 11) {  // uniform static E, B
         ax = c.tE[0]; ay = c.tE[1]; az = c.tE[2];
         bx = c.tB[0]; by = c.tB[1]; bz = c.tB[2];
     } else if constexpr (FIELD == 10) {  // plane wave, x polarized
-        const double d = tau - Z;
         const double s = d * c.inv_T0n;
         double sn, cs;
         fm::sincos_f64(d + c.phi0, &sn, &cs);
-        const double e = c.a0 * fm::exp_f64(-s * s) * cs;
+        const double e = c.a0 * fm::exp_fin_f64(-s * s) * cs;
         ax = e; ay = 0.0; az = 0.0;
         bx = 0.0; by = e; bz = 0.0;
+    } else if constexpr (FIELD == 21 || FIELD == 23 || FIELD == 25) {
+        lp_field_f64<FIELD - 20, WANT_B, CFG>(c, X, Y, Z, d, ax, ay, az, bx, by, bz);
     } else {
-        rp_field_f64<FIELD, WANT_B, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by);
+        rp_field_f64<FIELD, WANT_B, LO, CFG>(c, X, Y, Z, d, dl, ax, ay, az, bx, by);
         bz = 0.0;
     }
 }
@@ -264,6 +422,8 @@ __device__ inline double bound2_f64(const CFG& c, double X, double Y, double Z)
         return c.tE[0] * c.tE[0] + c.tE[1] * c.tE[1] + c.tE[2] * c.tE[2];
     else if constexpr (FIELD == 10)
         return c.a0 * c.a0;
+    else if constexpr (FIELD == 21 || FIELD == 23 || FIELD == 25)
+        return lp_bound2<FIELD - 20, CFG>(c, X, Y, Z);
     else
         return rp_bound2<FIELD, CFG>(c, X, Y, Z);
 }

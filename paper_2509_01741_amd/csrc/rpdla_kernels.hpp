@@ -82,10 +82,10 @@ __global__ void __launch_bounds__(256) birth_phase_kernel(
 // skipped: before each state's possible window and after it.
 // ---------------------------------------------------------------------------
 template <int FIELD, class CFG>
-__device__ inline double emag2_f64(const CFG& c, double X, double Y, double Z, double tau)
+__device__ inline double emag2_f64(const CFG& c, double X, double Y, double Z, double d)
 {
     double ax, ay, az, bx, by, bz;
-    field_f64<FIELD, false, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
+    field_f64<FIELD, false, CFG>(c, X, Y, Z, d, ax, ay, az, bx, by, bz);
     return ax * ax + ay * ay + az * az;
 }
 
@@ -112,7 +112,7 @@ __device__ inline AtomGeom atom_geom(const CFG& c, double X, double Y, double Z)
         const double rD = r2 * iD;
         a.r2 = r2;
         a.mrD = -rD;
-        a.psi_c = c.phi0 - Z - rD * zeta;
+        a.psi_c = c.phi0 - rD * zeta;
         const Cx<double> q{iD, zeta * iD};
         const double r4 = r2 * r2, r6 = r4 * r2, r8 = r4 * r4;
         // P_E(q) = sum p_n q^n and P_Z(q) = sum z_n q^n, by Horner in q
@@ -151,25 +151,25 @@ __device__ inline AtomGeom atom_geom(const CFG& c, double X, double Y, double Z)
 }
 
 template <int FIELD, class CFG>
-__device__ inline double emag2_atom(const CFG& c, const AtomGeom& a, double tau)
+__device__ inline double emag2_atom(const CFG& c, const AtomGeom& a, double d)
 {
     if constexpr (FIELD == 1 || FIELD == 3 || FIELD == 5) {
-        const double s = (tau - a.Z) * c.inv_T0n;
+        const double s = d * c.inv_T0n;
         const double g = c.a0 * fm::exp_f64(a.mrD - s * s);
         double sn, cs;
-        fm::sincos_f64(tau + a.psi_c, &sn, &cs);
+        fm::sincos2_f64(d, a.psi_c, &sn, &cs);
         const double et = c.er_scale * g * (cs * a.aer - sn * a.aei);
         const double ez = c.ez_scale * g * (sn * a.azr + cs * a.azi);
         return et * et * a.r2 + ez * ez;
     } else {
-        return emag2_f64<FIELD>(c, a.X, a.Y, a.Z, tau);
+        return emag2_f64<FIELD>(c, a.X, a.Y, a.Z, d);
     }
 }
 
 template <int FIELD, class CFG>
-__device__ inline double rate_at(const CFG& c, const AdkState& st, const AtomGeom& a, double tau)
+__device__ inline double rate_at(const CFG& c, const AdkState& st, const AtomGeom& a, double d)
 {
-    return adk_rate_n(st, emag2_atom<FIELD>(c, a, tau));
+    return adk_rate_n(st, emag2_atom<FIELD>(c, a, d));
 }
 
 // GL-4 estimate of the integral of the rate over [a, b]; the nodes are
@@ -231,45 +231,49 @@ __device__ inline bool state_window(const CFG& c, const AdkState& st, double bou
 }
 
 // Birth times of one atom (index `atom`, normalized position X, Y, Z) for
-// states k_first..k_first+K-1, written to out[0..K) in seconds.
+// states k_first..k_first+K-1, written to out[0..K) in seconds.  The atom is
+// at rest, so its field depends on time only through the retarded time
+// d = tau - Z: the panels, nodes and crossings are all taken in d (the same
+// grid as in tau, shifted by Z), so the carrier phase is formed from d itself
+// and the birth time tau = d + Z is rounded once, at the output.
 template <int FIELD, class CFG>
 __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t atom, double X,
                             double Y, double Z, int k_first, int K, double* __restrict__ out)
 {
     for (int s = 0; s < K; ++s) out[s] = __builtin_inf();
-    const double tz = (c.window == 0) ? Z : 0.0;
-    const double tau_s = tz - c.tb_n, tau_e = tz + c.ta_n;
+    const double dz = (c.window == 0) ? 0.0 : -Z;   // window start relative to arrival
+    const double d_s = dz - c.tb_n, d_e = dz + c.ta_n;
     const double h = c.hn;
-    const int64_t M = (int64_t)ceil((tau_e - tau_s) / h);
+    const int64_t M = (int64_t)ceil((d_e - d_s) / h);
     const double b2 = bound2_f64<FIELD>(c, X, Y, Z);
-    const double Zc = Z;  // the envelope peaks at tau = Z for the pulse models
+    const double Zc = 0.0;  // the envelope peaks at d = 0 for the pulse models
     const AtomGeom ag = atom_geom<FIELD>(c, X, Y, Z);
 
     int s = 0;
     double target = -log(uniform_j(seed, cfg, atom, k_first + 2));
     // states with a zero threshold are born where they start
     while (s < K && !(target > 0.0)) {
-        out[s] = tau_s * c.inv_omega;
+        out[s] = (d_s + Z) * c.inv_omega;
         ++s;
         if (s < K) target = -log(uniform_j(seed, cfg, atom, k_first + s + 2));
     }
     if (s >= K) return;
     AdkState st = adk_state(c, k_first - 1 + s);
     int64_t j_lo, j_hi;
-    if (!state_window(c, st, b2, Zc, tau_s, h, M, j_lo, j_hi)) return;
+    if (!state_window(c, st, b2, Zc, d_s, h, M, j_lo, j_hi)) return;
     double I = 0.0;
-    double tstart = tau_s;
+    double tstart = d_s;
     for (int64_t j = j_lo; j < M; ++j) {
         if (j > j_hi) break;
-        const double a = tau_s + (double)j * h;
-        const double b = (j == M - 1) ? tau_e : tau_s + (double)(j + 1) * h;
+        const double a = d_s + (double)j * h;
+        const double b = (j == M - 1) ? d_e : d_s + (double)(j + 1) * h;
         bool done = false;
         while (true) {
             const double lo = (tstart > a) ? tstart : a;
             const double seg = gl4_integral<FIELD>(c, st, ag, lo, b);
             if (I + seg < target) { I += seg; break; }
             const double t = solve_crossing<FIELD>(c, st, ag, lo, b, target - I, seg);
-            out[s] = t * c.inv_omega;
+            out[s] = (t + Z) * c.inv_omega;
             ++s;
             if (s >= K) { done = true; break; }
             target = -log(uniform_j(seed, cfg, atom, k_first + s + 2));
@@ -277,7 +281,7 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
             tstart = t;
             st = adk_state(c, k_first - 1 + s);
             int64_t nlo, nhi;
-            if (!state_window(c, st, b2, Zc, tau_s, h, M, nlo, nhi)) {
+            if (!state_window(c, st, b2, Zc, d_s, h, M, nlo, nhi)) {
                 if (!(target > 0.0)) { j_hi = M - 1; continue; }
                 done = true;
                 break;
@@ -304,26 +308,62 @@ __global__ void __launch_bounds__(256, 3) ionize_kernel(
 // ---------------------------------------------------------------------------
 // Push.  One electron per lane: state (X, u) advanced by classical RK4 with
 // fixed step h from its birth to the end of its atom's window (steps start at
-// tau0 + n h, the last one ends on the window end).
+// tau0 + n h, the last one ends on the window end).  The fields depend on
+// time only through the retarded time D = tau - Z, which the state carries as
+// a seventh variable (dD/dtau = 1 - u_z/gamma, D = tau0 - Z0 at birth): RK4
+// is linear in its stage slopes, so in exact arithmetic D equals tau - Z at
+// every stage, while in floating point the carrier phase is resolved to the
+// rounding of D itself rather than that of tau and Z separately (each up to
+// ~1e3 over the window).
 // ---------------------------------------------------------------------------
 template <int FIELD, class CFG>
-__device__ inline void rhs_f64(const CFG& c, double tau, double X, double Y, double Z, double ux,
-                               double uy, double uz, double& dX, double& dY, double& dZ,
-                               double& dux, double& duy, double& duz)
+__device__ inline void rhs_f64(const CFG& c, double d, double dl, double X, double Y, double Z,
+                               double ux, double uy, double uz, double& dX, double& dY,
+                               double& dZ, double& dux, double& duy, double& duz)
 {
-    double ax, ay, az, bx, by, bz;
-    field_f64<FIELD, true, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
     const double ig = fm::rsqrt_ge1_f64(1.0 + ux * ux + uy * uy + uz * uz);
     dX = ux * ig; dY = uy * ig; dZ = uz * ig;
-    dux = -(ax + dY * bz - dZ * by);
-    duy = -(ay + dZ * bx - dX * bz);
-    duz = -(az + dX * by - dY * bx);
+    if constexpr (FIELD == 1 || FIELD == 3 || FIELD == 5) {
+        // radial field: a = (pe X, pe Y, az), b = pb (-Y, X, 0), so
+        // a + beta x b = ((pe - beta_z pb) X, (pe - beta_z pb) Y,
+        //                 az + pb (beta_x X + beta_y Y))
+        double pe, pb, az;
+        rp_field_parts_f64<FIELD, true>(c, X, Y, Z, d, dl, pe, pb, az);
+        const double f = fma(-dZ, pb, pe);
+        dux = -f * X;
+        duy = -f * Y;
+        duz = -fma(pb, fma(dY, Y, dX * X), az);
+    } else {
+        double ax, ay, az, bx, by, bz;
+        field_f64<FIELD, true, CFG>(c, X, Y, Z, d + dl, ax, ay, az, bx, by, bz);
+        dux = -(ax + dY * bz - dZ * by);
+        duy = -(ay + dZ * bx - dX * bz);
+        duz = -(az + dX * by - dY * bx);
+    }
 }
 
+// The state is accumulated with compensated (Kahan) summation: over the
+// ~3e4 steps of a trajectory the rounding of plain double accumulation,
+// above all of the position, is amplified to more than 1e-8 of the final
+// energy for a few electrons in a thousand; the compensation terms cX..cuz
+// carry what each addition lost into the next one.
 struct ElecF64 {
     double X, Y, Z, ux, uy, uz, tau0, taue;
+    double D;                                  // retarded time tau - Z
+    double cX, cY, cZ, cux, cuy, cuz, cD;
     int64_t n, N;
 };
+
+constexpr double kLightSpeed = 299792458.0;            // m/s, exact
+constexpr double kInvLightSpeed = 1.0 / 299792458.0;
+
+__device__ inline void kahan_add_f64(double& s, double& comp, double v)
+{
+    const double y = v - comp;
+    const double t = s + y;
+    comp = (t - s) - y;
+    s = t;
+}
 
 // Set up an electron born at rest at t0 [s] at atom position (x, y, z) [m].
 // Returns false (invalid slot) for a birth more than one step before the
@@ -333,7 +373,13 @@ __device__ inline bool elec_init(const CFG& c, ElecF64& e, double t0, double x, 
 {
     e.X = x * c.k; e.Y = y * c.k; e.Z = z * c.k;
     e.ux = e.uy = e.uz = 0.0;
+    e.cX = e.cY = e.cZ = e.cux = e.cuy = e.cuz = e.cD = 0.0;
     e.tau0 = t0 * c.omega;
+    // D = omega (t0 - z0/c), the quotient z0/c carried with its remainder so
+    // that the retarded time is formed to the rounding of its own value
+    const double zc = z * kInvLightSpeed;
+    const double zr = fma(-zc, kLightSpeed, z);
+    e.D = ((t0 - zc) - zr * kInvLightSpeed) * c.omega;
     const double tz = (c.window == 0) ? e.Z : 0.0;
     e.taue = tz + c.ta_n;
     e.n = 0;
@@ -351,21 +397,31 @@ __device__ inline void elec_step(const CFG& c, ElecF64& e)
     const double hs = (e.n == e.N - 1) ? (e.taue - ta) : h;
     const double hh = 0.5 * hs;
     double kX, kY, kZ, kx, ky, kz, aX, aY, aZ, ax, ay, az;
-    rhs_f64<FIELD>(c, ta, e.X, e.Y, e.Z, e.ux, e.uy, e.uz, kX, kY, kZ, kx, ky, kz);
+    rhs_f64<FIELD>(c, e.D, -e.cD, e.X, e.Y, e.Z, e.ux, e.uy, e.uz, kX, kY, kZ, kx, ky, kz);
     aX = kX; aY = kY; aZ = kZ; ax = kx; ay = ky; az = kz;
-    rhs_f64<FIELD>(c, ta + hh, e.X + hh * kX, e.Y + hh * kY, e.Z + hh * kZ, e.ux + hh * kx,
-                   e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_f64<FIELD>(c, e.D, fma(hh, 1.0 - kZ, -e.cD), e.X + hh * kX, e.Y + hh * kY,
+                   e.Z + hh * kZ, e.ux + hh * kx, e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx,
+                   ky, kz);
     aX += 2.0 * kX; aY += 2.0 * kY; aZ += 2.0 * kZ;
     ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
-    rhs_f64<FIELD>(c, ta + hh, e.X + hh * kX, e.Y + hh * kY, e.Z + hh * kZ, e.ux + hh * kx,
-                   e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_f64<FIELD>(c, e.D, fma(hh, 1.0 - kZ, -e.cD), e.X + hh * kX, e.Y + hh * kY,
+                   e.Z + hh * kZ, e.ux + hh * kx, e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx,
+                   ky, kz);
     aX += 2.0 * kX; aY += 2.0 * kY; aZ += 2.0 * kZ;
     ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
-    rhs_f64<FIELD>(c, ta + hs, e.X + hs * kX, e.Y + hs * kY, e.Z + hs * kZ, e.ux + hs * kx,
-                   e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_f64<FIELD>(c, e.D, fma(hs, 1.0 - kZ, -e.cD), e.X + hs * kX, e.Y + hs * kY,
+                   e.Z + hs * kZ, e.ux + hs * kx, e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx,
+                   ky, kz);
     const double w6 = hs * (1.0 / 6.0);
-    e.X += w6 * (aX + kX); e.Y += w6 * (aY + kY); e.Z += w6 * (aZ + kZ);
-    e.ux += w6 * (ax + kx); e.uy += w6 * (ay + ky); e.uz += w6 * (az + kz);
+    const double sZ = aZ + kZ;
+    kahan_add_f64(e.X, e.cX, w6 * (aX + kX));
+    kahan_add_f64(e.Y, e.cY, w6 * (aY + kY));
+    kahan_add_f64(e.Z, e.cZ, w6 * sZ);
+    kahan_add_f64(e.ux, e.cux, w6 * (ax + kx));
+    kahan_add_f64(e.uy, e.cuy, w6 * (ay + ky));
+    kahan_add_f64(e.uz, e.cuz, w6 * (az + kz));
+    // the weighted slopes of D sum to 6 - sZ
+    kahan_add_f64(e.D, e.cD, w6 * (6.0 - sZ));
     ++e.n;
 }
 
@@ -392,12 +448,12 @@ struct ElecRR : ElecF64 {
 
 // Right-hand side with the radiation term; returns gamma^2 Q at the state.
 template <int FIELD, bool RR, class CFG>
-__device__ inline double rhs_rr_f64(const CFG& c, double tau, double X, double Y, double Z,
+__device__ inline double rhs_rr_f64(const CFG& c, double d, double dl, double X, double Y, double Z,
                                     double ux, double uy, double uz, double& dX, double& dY,
                                     double& dZ, double& dux, double& duy, double& duz)
 {
     double ax, ay, az, bx, by, bz;
-    field_f64<FIELD, true, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
+    field_f64<FIELD, true, CFG, true>(c, X, Y, Z, d, ax, ay, az, bx, by, bz, dl);
     const double ig = fm::rsqrt_ge1_f64(1.0 + ux * ux + uy * uy + uz * uz);
     dX = ux * ig; dY = uy * ig; dZ = uz * ig;
     const double fx = ax + (dY * bz - dZ * by);
@@ -430,23 +486,32 @@ __device__ inline void elec_step(const CFG& c, ElecRR<RR>& e)
     const double hs = (e.n == e.N - 1) ? (e.taue - ta) : h;
     const double hh = 0.5 * hs;
     double kX, kY, kZ, kx, ky, kz, aX, aY, aZ, ax, ay, az;
-    const double g2q = rhs_rr_f64<FIELD, RR>(c, ta, e.X, e.Y, e.Z, e.ux, e.uy, e.uz, kX, kY, kZ,
-                                             kx, ky, kz);
+    const double g2q = rhs_rr_f64<FIELD, RR>(c, e.D, -e.cD, e.X, e.Y, e.Z, e.ux, e.uy, e.uz, kX,
+                                             kY, kZ, kx, ky, kz);
     e.g2q = g2q > e.g2q ? g2q : e.g2q;
     aX = kX; aY = kY; aZ = kZ; ax = kx; ay = ky; az = kz;
-    rhs_rr_f64<FIELD, RR>(c, ta + hh, e.X + hh * kX, e.Y + hh * kY, e.Z + hh * kZ, e.ux + hh * kx,
-                          e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_rr_f64<FIELD, RR>(c, e.D, fma(hh, 1.0 - kZ, -e.cD), e.X + hh * kX, e.Y + hh * kY,
+                          e.Z + hh * kZ, e.ux + hh * kx, e.uy + hh * ky, e.uz + hh * kz, kX, kY,
+                          kZ, kx, ky, kz);
     aX += 2.0 * kX; aY += 2.0 * kY; aZ += 2.0 * kZ;
     ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
-    rhs_rr_f64<FIELD, RR>(c, ta + hh, e.X + hh * kX, e.Y + hh * kY, e.Z + hh * kZ, e.ux + hh * kx,
-                          e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_rr_f64<FIELD, RR>(c, e.D, fma(hh, 1.0 - kZ, -e.cD), e.X + hh * kX, e.Y + hh * kY,
+                          e.Z + hh * kZ, e.ux + hh * kx, e.uy + hh * ky, e.uz + hh * kz, kX, kY,
+                          kZ, kx, ky, kz);
     aX += 2.0 * kX; aY += 2.0 * kY; aZ += 2.0 * kZ;
     ax += 2.0 * kx; ay += 2.0 * ky; az += 2.0 * kz;
-    rhs_rr_f64<FIELD, RR>(c, ta + hs, e.X + hs * kX, e.Y + hs * kY, e.Z + hs * kZ, e.ux + hs * kx,
-                          e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_rr_f64<FIELD, RR>(c, e.D, fma(hs, 1.0 - kZ, -e.cD), e.X + hs * kX, e.Y + hs * kY,
+                          e.Z + hs * kZ, e.ux + hs * kx, e.uy + hs * ky, e.uz + hs * kz, kX, kY,
+                          kZ, kx, ky, kz);
     const double w6 = hs * (1.0 / 6.0);
-    e.X += w6 * (aX + kX); e.Y += w6 * (aY + kY); e.Z += w6 * (aZ + kZ);
-    e.ux += w6 * (ax + kx); e.uy += w6 * (ay + ky); e.uz += w6 * (az + kz);
+    const double sZ = aZ + kZ;
+    kahan_add_f64(e.X, e.cX, w6 * (aX + kX));
+    kahan_add_f64(e.Y, e.cY, w6 * (aY + kY));
+    kahan_add_f64(e.Z, e.cZ, w6 * sZ);
+    kahan_add_f64(e.ux, e.cux, w6 * (ax + kx));
+    kahan_add_f64(e.uy, e.cuy, w6 * (ay + ky));
+    kahan_add_f64(e.uz, e.cuz, w6 * (az + kz));
+    kahan_add_f64(e.D, e.cD, w6 * (6.0 - sZ));
     ++e.n;
 }
 
@@ -516,7 +581,8 @@ __device__ inline bool elec_init(const CFG& c, ElecDP& e, double t0, double x, d
 template <int FIELD, class CFG>
 __device__ inline void dp_rhs(const CFG& c, double tau, const double* y, double* k)
 {
-    rhs_f64<FIELD>(c, tau, y[0], y[1], y[2], y[3], y[4], y[5], k[0], k[1], k[2], k[3], k[4], k[5]);
+    rhs_f64<FIELD>(c, tau - y[2], 0.0, y[0], y[1], y[2], y[3], y[4], y[5], k[0], k[1], k[2], k[3],
+                   k[4], k[5]);
 }
 
 template <int FIELD, class CFG>
@@ -612,8 +678,8 @@ __device__ inline void elec_final(const CFG& c, const ElecDP& e, double& ux, dou
 // a Kahan compensation term.
 // ---------------------------------------------------------------------------
 template <int ORDER, class CFG>
-__device__ inline void rp_field_mixed(const CFG& c, double X, double Y, double Z, double tau,
-                                      float& ax, float& ay, float& az, float& bx, float& by)
+__device__ inline void rp_field_parts_mixed(const CFG& c, double X, double Y, double Z, double tau,
+                                            float& pe, float& pb, float& az)
 {
     const double d = tau - Z;
     double turns = d * kInvTwoPi;
@@ -627,14 +693,22 @@ __device__ inline void rp_field_mixed(const CFG& c, double X, double Y, double Z
     const float s = (float)(d * c.inv_T0n);
     const float g = (float)c.a0 * __builtin_amdgcn_exp2f(-(rD + s * s) * 1.4426950408889634f);
     const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-    Cx<float> Q[9];
-    rp_amplitudes<ORDER, float>(g, cs, sn, Cx<float>{iD, zeta * iD}, Q);
-    float PE, PB, EZ;
-    rp_combine<ORDER, float>(Q, r2, (float)c.eps, (float)c.e2, (float)c.e3, (float)c.e4, PE, PB,
-                             EZ);
-    const float pe = (float)c.er_scale * PE * (float)c.inv_w0n;
-    const float pb = PB * (float)c.inv_w0n;
-    ax = pe * Xf; ay = pe * Yf; az = (float)c.ez_scale * EZ;
+    const float gi = g * (iD * iD);
+    float PE, PB, EZe;
+    rp_brackets<ORDER, float>(gi * cs, gi * sn, zeta, rD, (float)c.e2 * iD, PE, PB, EZe);
+    pe = (float)c.er_w * PE;
+    pb = PB * (float)c.inv_w0n;
+    az = (float)c.ez_e * EZe;
+}
+
+template <int ORDER, class CFG>
+__device__ inline void rp_field_mixed(const CFG& c, double X, double Y, double Z, double tau,
+                                      float& ax, float& ay, float& az, float& bx, float& by)
+{
+    float pe, pb;
+    rp_field_parts_mixed<ORDER>(c, X, Y, Z, tau, pe, pb, az);
+    const float Xf = (float)X, Yf = (float)Y;
+    ax = pe * Xf; ay = pe * Yf;
     bx = -pb * Yf; by = pb * Xf;
 }
 
@@ -643,6 +717,7 @@ __device__ inline void field_mixed(const CFG& c, double X, double Y, double Z, d
                                    float& ax, float& ay, float& az, float& bx, float& by,
                                    float& bz)
 {
+    static_assert(FIELD < 20, "the linearly polarized focus has no mixed form");
     if constexpr (FIELD == 11) {
         ax = (float)c.tE[0]; ay = (float)c.tE[1]; az = (float)c.tE[2];
         bx = (float)c.tB[0]; by = (float)c.tB[1]; bz = (float)c.tB[2];
@@ -665,13 +740,24 @@ __device__ inline void rhs_mixed(const CFG& c, double tau, double X, double Y, d
                                  float uy, float uz, float& dX, float& dY, float& dZ, float& dux,
                                  float& duy, float& duz)
 {
-    float ax, ay, az, bx, by, bz;
-    field_mixed<FIELD, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
     const float ig = __builtin_amdgcn_rsqf(1.0f + ux * ux + uy * uy + uz * uz);
     dX = ux * ig; dY = uy * ig; dZ = uz * ig;
-    dux = -(ax + dY * bz - dZ * by);
-    duy = -(ay + dZ * bx - dX * bz);
-    duz = -(az + dX * by - dY * bx);
+    if constexpr (FIELD == 1 || FIELD == 3 || FIELD == 5) {
+        // radial field: the force from its radial and axial parts, as in rhs_f64
+        float pe, pb, az;
+        rp_field_parts_mixed<FIELD>(c, X, Y, Z, tau, pe, pb, az);
+        const float Xf = (float)X, Yf = (float)Y;
+        const float f = fmaf(-dZ, pb, pe);
+        dux = -f * Xf;
+        duy = -f * Yf;
+        duz = -fmaf(pb, fmaf(dY, Yf, dX * Xf), az);
+    } else {
+        float ax, ay, az, bx, by, bz;
+        field_mixed<FIELD, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
+        dux = -(ax + dY * bz - dZ * by);
+        duy = -(ay + dZ * bx - dX * bz);
+        duz = -(az + dX * by - dY * bx);
+    }
 }
 
 __device__ inline void kahan_add(float& s, float& comp, float v)
@@ -724,8 +810,8 @@ __device__ inline void elec_step(const CFG& c, ElecMixed& e)
     ax += 2.f * kx; ay += 2.f * ky; az += 2.f * kz;
     rhs_mixed<FIELD>(c, ta + hsd, e.X + hsd * kX, e.Y + hsd * kY, e.Z + hsd * kZ, e.ux + hs * kx,
                      e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx, ky, kz);
-    const double w6d = hsd / 6.0;
-    const float w6 = hs / 6.0f;
+    const double w6d = hsd * (1.0 / 6.0);
+    const float w6 = hs * (1.0f / 6.0f);
     e.X += w6d * (double)(aX + kX); e.Y += w6d * (double)(aY + kY); e.Z += w6d * (double)(aZ + kZ);
     kahan_add(e.ux, e.cx, w6 * (ax + kx));
     kahan_add(e.uy, e.cy, w6 * (ay + ky));

@@ -15,7 +15,10 @@ Studies (the paper's figure each one mirrors, with synthetic seeded ions):
   * ``field_scale``     -- Fig. 9: yields with Ez or Er multiplied by s in
                            [0, 1], 5e19 W/cm^2;
   * ``wavelength_scan`` -- Fig. 5: energies for 0.8, 1 and 2 um at equal
-                           intensity and f-number.
+                           intensity and f-number;
+  * ``polarization``    -- Fig. 4: the radially polarized focus against the
+                           linearly polarized one at the same intensity,
+                           wavelength and f-number (backward electrons).
 
 Paper set-up (Sec. 2.2): 800 nm unless stated, f/5, 53 fs pulses, Ne7+ ions
 at rest freeing their eighth electron (charge state 8 only), targets of
@@ -70,7 +73,10 @@ def run(L: B.rpdla_laser, n_atoms: int, r_out: float, *, r_in: float = 0.0,
     spa = k_last - k_first + 1
     ux, uy, uz, xf, yf, zf = B.rpdla_push(L, precision, tb, x, y, z, spa, stream=stream)
     K, theta, psi, fwd = B.rpdla_epilogue(ux, uy, uz, stream=stream)
-    phase, rb = B.rpdla_birth_phase(L, tb, x, y, z, spa, stream=stream)
+    phase = rb = None
+    if L.field not in (B.RPDLA_LP_O1, B.RPDLA_LP_O3, B.RPDLA_LP_O5):
+        # the birth phase is the radial focus's carrier phase
+        phase, rb = B.rpdla_birth_phase(L, tb, x, y, z, spa, stream=stream)
     return dict(x=x, y=y, z=z, t_birth=tb, ux=ux, uy=uy, uz=uz, xf=xf, yf=yf, zf=zf, K=K,
                 theta=theta, psi=psi, fwd=fwd, phase=phase, r_birth=rb, slots_per_atom=spa)
 
@@ -194,9 +200,22 @@ def study_wavelength_scan(n_atoms: int, lams=(0.8 * UM, 1.0 * UM, 2.0 * UM),
     return out
 
 
+def study_polarization(n_atoms: int, intensities=(5e19, 5e20, 5e21), r_target: float = 1 * UM,
+                       seed: int = 0) -> list:
+    """Fig. 4: radially against linearly polarized focus, same intensity,
+    wavelength, f-number and pulse, the same seeded ions."""
+    out = []
+    for i, I in enumerate(intensities):
+        for name, order in (("radial", B.RPDLA_RP_O5), ("linear", B.RPDLA_LP_O5)):
+            res = run(paper_laser(I, order=order), n_atoms, r_target, seed=seed,
+                      cfg_id=600 + i)
+            out.append(dict(I_W_cm2=I, polarization=name, **yields(res)))
+    return out
+
+
 STUDIES = dict(birth_maps=study_birth_maps, target_radius=study_target_radius,
                hollow_scan=study_hollow_scan, field_scale=study_field_scale,
-               wavelength_scan=study_wavelength_scan)
+               wavelength_scan=study_wavelength_scan, polarization=study_polarization)
 
 
 def main(argv=None) -> int:

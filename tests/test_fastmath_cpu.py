@@ -18,8 +18,14 @@ HARNESS = r'''
 extern "C" void fm_sincos(long n, const double* x, double* s, double* c) {
     for (long i = 0; i < n; ++i) rpdla::fm::sincos_f64(x[i], s + i, c + i);
 }
+extern "C" void fm_sincos2(long n, const double* xh, const double* xl, double* s, double* c) {
+    for (long i = 0; i < n; ++i) rpdla::fm::sincos2_f64(xh[i], xl[i], s + i, c + i);
+}
 extern "C" void fm_exp(long n, const double* x, double* y) {
     for (long i = 0; i < n; ++i) y[i] = rpdla::fm::exp_f64(x[i]);
+}
+extern "C" void fm_exp_fin(long n, const double* x, double* y) {
+    for (long i = 0; i < n; ++i) y[i] = rpdla::fm::exp_fin_f64(x[i]);
 }
 extern "C" void fm_rcp(long n, const double* x, double* y) {
     for (long i = 0; i < n; ++i) y[i] = rpdla::fm::rcp_f64(x[i]);
@@ -42,6 +48,8 @@ def fm(tmp_path_factory):
     P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
     lib.fm_sincos.argtypes = [C.c_long, P, P, P]
     lib.fm_exp.argtypes = [C.c_long, P, P]
+    lib.fm_sincos2.argtypes = [C.c_long, P, P, P, P]
+    lib.fm_exp_fin.argtypes = [C.c_long, P, P]
     lib.fm_rcp.argtypes = [C.c_long, P, P]
     lib.fm_rsqrt.argtypes = [C.c_long, P, P]
     return lib
@@ -73,6 +81,28 @@ def test_sincos_against_mpmath(fm):
         assert abs(ci - mp.cos(xs)) <= 2 * 2.0**-53
 
 
+def test_sincos_of_unevaluated_sum(fm):
+    """sin and cos of x_hi + x_lo taken exactly (mpmath) for phases up to 1e3
+    with a low part of a few units: a few 2^-53 absolute, well below
+    ulp(x_hi) -- the precision a rounded sum x_hi + x_lo would have lost."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.prec = 120
+    rng = np.random.default_rng(7)
+    xh = rng.uniform(-1e3, 1e3, 3000)
+    xl = rng.uniform(-4, 4, 3000)
+    s = np.zeros_like(xh); c = np.zeros_like(xh)
+    fm.fm_sincos2(xh.size, xh, xl, s, c)
+    ref_s = np.array([float(mp.sin(mp.mpf(a) + mp.mpf(b))) for a, b in zip(xh, xl)])
+    ref_c = np.array([float(mp.cos(mp.mpf(a) + mp.mpf(b))) for a, b in zip(xh, xl)])
+    es = np.abs(s - ref_s) / 2.0**-53
+    ec = np.abs(c - ref_c) / 2.0**-53
+    assert es.max() <= 8 and ec.max() <= 8, (es.max(), ec.max())
+    # the rounded sum loses up to ulp(1e3)/2 = 2^-44 of argument
+    s1 = np.zeros_like(xh); c1 = np.zeros_like(xh)
+    fm.fm_sincos(xh.size, xh + xl, s1, c1)
+    assert np.abs(s1 - ref_s).max() / 2.0**-53 > 4 * es.max()
+
+
 def test_exp_against_libm(fm):
     rng = np.random.default_rng(3)
     x = np.concatenate([rng.uniform(-745, 5, 400000), rng.uniform(-1, 1, 100000),
@@ -85,6 +115,23 @@ def test_exp_against_libm(fm):
     assert rel.max() <= 3 * 2.0**-53, rel.max()
     assert np.all(np.abs(y[~norm] - ref[~norm]) <= 4.9e-324 * 4)
     assert fm and y[-6] == 1.0 and y[-1] == 0.0 and y[-2] == 0.0
+
+
+def test_exp_without_guards_equals_exp(fm):
+    """The guard-free exponential of the field evaluations returns what the
+    guarded one does wherever the guards do not act, and flushes to zero (or
+    the smallest denormal, correctly rounded) far below the normal range."""
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.uniform(-745, 5, 400000), rng.uniform(-1, 1, 100000),
+                        rng.uniform(-1e5, -745.2, 10000), [0.0, -708.0, -745.0, -1e5]])
+    y = np.zeros_like(x); yf = np.zeros_like(x)
+    fm.fm_exp(x.size, x, y)
+    fm.fm_exp_fin(x.size, x, yf)
+    guarded = x < -745.2
+    assert np.array_equal(y[~guarded], yf[~guarded])
+    assert np.all(yf[guarded] == 0.0)
+    ref = np.exp(x[~guarded])
+    assert np.all(np.abs(yf[~guarded] - ref) <= np.maximum(3 * 2.0**-53 * ref, 4 * 4.9e-324))
 
 
 def test_rcp(fm):

@@ -106,3 +106,31 @@ def test_batched_mixed_precision(env):
     # energy spectra agree bin-for-bin up to electrons near bin edges
     d = np.abs(c64.cpu().numpy() - cmx.cpu().numpy()).sum(axis=(1, 2, 3))
     assert np.all(d <= 0.1 * nb + 2), d
+
+
+def test_single_chunk_graph_replays(env):
+    """A one-chunk sweep on a side stream is captured into a graph once and
+    replayed: three calls with the same buffers, with the program's own eager
+    work and synchronizations between them, each equal to the eager result on
+    the null stream."""
+    torch, B, O = env
+    lasers = _lasers(B)
+    spec = B.rpdla_hist_spec(*SPEC)
+    n, K = 40, 10
+    c0, t0 = B.rpdla_run_batched(lasers, 6, 11, n, n, 2.0, 1, K, 0, spec)   # null stream: eager
+    torch.cuda.synchronize()
+    g0 = B.rpdla_batched_graphs()
+    s = torch.cuda.Stream()
+    counts = torch.zeros_like(c0)
+    tallies = torch.zeros_like(t0)
+    ws = torch.empty(B.rpdla_batched_workspace_bytes(3, n, 1, K), dtype=torch.uint8, device="cuda")
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            counts.zero_()
+            tallies.zero_()
+            B.rpdla_run_batched(lasers, 6, 11, n, n, 2.0, 1, K, 0, spec, counts, tallies, ws,
+                                stream=s)
+        s.synchronize()
+        assert float(torch.arange(1000, device="cuda", dtype=torch.float64).sum()) == 499500.0
+        assert torch.equal(counts, c0) and torch.equal(tallies, t0), rep
+        assert B.rpdla_batched_graphs() == g0 + 1
