@@ -26,10 +26,17 @@ if ROOT not in sys.path:
 
 C_LIGHT = 299792458.0
 # FP64 floating-point operations of one RK4 step of one electron with the
-# order-5 field (mul, add = 1 FLOP, fma = 2; the sine/cosine, exponential,
-# reciprocal and reciprocal square root counted at the operations of their
-# polynomial implementations): 4 x (223 field + 27 Lorentz) + 85 RK4 = 1085.
-ALGO_FLOP_PER_STEP = 1085.0
+# order-5 radial field, counted from the implemented formulas (mul, add and
+# the hardware reciprocal / reciprocal-square-root estimates = 1 FLOP,
+# fma = 2; the sine/cosine, exponential, reciprocal and reciprocal square root
+# at the operations of their polynomial and Newton sequences).  Per
+# right-hand side: field 191 (position terms 8, reciprocal 9, phase and
+# envelope arguments 7, exponential 29, sine/cosine of the two-part phase 43,
+# amplitude 5, w-recurrence 30, brackets 57, radial and axial scales 3) +
+# Lorentz 30 (gamma 18, velocity 3, force from the radial parts 9); per step
+# 4 x 221 + RK4 115 (stage arguments 48, slope sums 24, increments 15,
+# compensated sums of the seven state variables 28) = 999.
+ALGO_FLOP_PER_STEP = 999.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # Published FP32 vector peak.  It counts packed FP32 FMAs (two per lane per
 # instruction); the kernels are compiled without packed FP32, so an FP32
@@ -37,12 +44,21 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # the ceiling for their unpacked FP32 FMAs is the FP64 figure, 78.6 TFLOP/s.
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 PROFILE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "push_rp_ne_fp64_100k_counters.json")
+# two counter passes (one rocprofv3 run each): instruction and FLOP counts,
+# then cycles, issue and lane activity
 COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32",
             "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
             "SQ_INSTS_VALU_TRANS_F32"]
-COUNTERS_CMD = ("rocprofv3 --pmc " + " ".join(COUNTERS) + " --output-format csv -d "
-                "$R/gpurun_out/pmcS -o run -- python3 $R/bench.py --steps 1 --warmup 0 --atoms 100000 "
-                "--no-cpu-baseline --no-adaptive --no-batched")
+COUNTERS2 = ["GRBM_GUI_ACTIVE", "GRBM_COUNT", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_BUSY_CU_CYCLES",
+             "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"]
+COUNTERS_RUN = ("rocprofv3 --pmc {ctrs} --output-format csv -d $R/gpurun_out/{d} -o run -- python3 "
+                "$R/bench.py --steps 1 --warmup 0 --atoms 100000 --no-cpu-baseline --no-adaptive "
+                "--no-batched")
+COUNTERS_CMD = COUNTERS_RUN.format(ctrs=" ".join(COUNTERS), d="pmcS")
+COUNTERS2_CMD = COUNTERS_RUN.format(ctrs=" ".join(COUNTERS2), d="pmcC")
+COUNTER_KERNELS = (("fp64", "push_kernel<5, rpdla::ElecF64>"),
+                   ("mixed", "push_kernel<5, rpdla::ElecMixed>"),
+                   ("ionize", "ionize_kernel<5>"))
 PROFILE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_fp64_rp_ne_fp64_1m_traffic.json")
 # sources that define the FP64 push kernel (its traffic figure is tied to them)
 KERNEL_SOURCES = ["rpdla_device.hpp", "rpdla_kernels.hpp", "rpdla_fastmath.hpp",
@@ -75,10 +91,33 @@ def electron_steps(tb, z, K, L):
     return int(n[fin].clamp(min=0).sum().item()), int(fin.sum().item())
 
 
-def cpu_baseline(ens, budget_s=15.0):
-    """Oracle push rate on a bounded sample of the same workload: the oracle
-    samples the first atoms and ionizes them itself (same seed and laser), and
-    its push over their slots is timed, scaled to ~budget_s."""
+# Atoms of the benchmark ensemble (the first ones, by index) on which the
+# oracle runs: its chain is timed for the CPU baseline and its results are
+# compared with the GPU's; the extended-precision reference for them is
+# stored under tests/golden (rp_ne_fp64_1m_head, 1200 atoms).
+ORACLE_SAMPLE_ATOMS = 600
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def kinetic_mev(u):
+    import numpy as np
+    u2 = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    return 0.51099895 * u2 / (np.sqrt(1.0 + u2) + 1.0)
+
+
+def cpu_baseline(ens, mixed_out=None):
+    """The oracle's whole chain (sampling, ionization, push, kinetic energy)
+    over the first ORACLE_SAMPLE_ATOMS atoms of the same ensemble, timed on
+    the host's cores; then its results against the GPU's (fp64_vs_oracle)."""
     import numpy as np
     import oracle as O
     wl = ens.wl
@@ -87,76 +126,83 @@ def cpu_baseline(ens, budget_s=15.0):
     OL.field = ens.L.field
     kf, kl = wl["k_first"], wl["k_last"]
     K = kl - kf + 1
-
-    def run(na):
-        x, y, z = O.sample_atoms(wl["seed"], wl["cfg_id"], 0, na, wl["r_factor"] * OL.w0,
-                                 O.rayleigh(OL))
-        t = O.ionize(OL, wl["seed"], wl["cfg_id"], 0, x, y, z, kf, kl)
-        fin = np.isfinite(t)
-        steps = np.ceil((np.repeat(z, K)[fin] / C_LIGHT + OL.t_after - t[fin]) / OL.dt).sum()
-        t0 = time.perf_counter()
-        out = O.push(OL, t, x, y, z, K)
-        return float(steps), time.perf_counter() - t0, (x, y, z, t, out)
-
-    s1, t1, _ = run(4)
-    na = int(max(4, min(ens.n, 4 * budget_s / max(t1, 1e-3))))
-    s2, t2, sample = run(na)
-    base = dict(value=s2 / t2, unit="electron-steps/s", cores=O.num_threads(), kind="oracle",
-                sample=f"FP64 push of the slots of the first {na} atoms ({int(s2)} electron-steps, "
-                       f"{t2:.1f} s), atoms and birth times from the oracle's own sampling and "
-                       f"ionization; order-5 field, same laser")
+    na = min(ORACLE_SAMPLE_ATOMS, ens.n)
+    t0 = time.perf_counter()
+    ch = O.chain(OL, wl["seed"], wl["cfg_id"], np.arange(na), wl["r_factor"] * OL.w0,
+                 O.rayleigh(OL), kf, kl)
+    secs = time.perf_counter() - t0
+    fin = np.isfinite(ch["t_birth"])
+    steps = float(np.ceil((np.repeat(ch["z"], K)[fin] / C_LIGHT + OL.t_after - ch["t_birth"][fin])
+                          / OL.dt).sum())
+    base = dict(value=steps / secs, unit="electron-steps/s", cores=O.num_threads(),
+                nproc=os.cpu_count(), cpu_model=cpu_model(), kind="oracle",
+                sample=f"the oracle's whole chain (sampling, ionization, FP64 push) over the first "
+                       f"{na} atoms of the same ensemble: {int(fin.sum())} electrons, "
+                       f"{int(steps)} electron-steps in {secs:.1f} s")
     try:
-        parity = fp64_vs_oracle(ens, OL, K, sample)
+        parity = fp64_vs_oracle(ens, OL, K, na, ch, mixed_out)
     except Exception as e:  # a reported statistic only
         log(f"FP64 vs oracle statistics unavailable: {e!r}")
         parity = None
     return base, parity
 
 
-def fp64_vs_oracle(ens, OL, K, sample):
-    """The GPU's FP64 results for the oracle's sample (the first atoms of the
-    same ensemble) against the oracle's: birth times, energies, directions.
-    Electrons outside 1e-8 are re-pushed by the oracle with birth times moved
-    by 1e-15 relative; those whose own energy then moves by more than 1e-10
-    are ill-conditioned (a rounding-level change of the input moves them)."""
+def fp64_vs_oracle(ens, OL, K, na, ch, mixed_out=None):
+    """The GPU's results for the oracle's sample against the oracle, every
+    electron classified by the rule of oracle/parity.py: birth times; final
+    energies against the double oracle's push of the GPU's own inputs and
+    against the extended-precision oracle's chain (stored reference);
+    directions; the mixed form against the extended reference."""
     import numpy as np
     import oracle as O
-    x, y, z, t, out = sample
-    n = t.size
+    from oracle import parity
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from golden.make_extended_refs import load
+    n = na * K
     tg = ens.tb[:n].cpu().numpy()
     ug = [o[:n].cpu().numpy() for o in ens.out[:3]]
+    gx = [a[:na].cpu().numpy() for a in (ens.x, ens.y, ens.z)]
     T = OL.lambda_ / C_LIGHT
-    fo, fg = np.isfinite(t), np.isfinite(tg)
+    fo, fg = np.isfinite(ch["t_birth"]), np.isfinite(tg)
     both = fo & fg
-    dt_rel = np.abs(t[both] - tg[both]) / np.maximum(np.abs(t[both]), T)
+    dt_rel = np.abs(ch["t_birth"][both] - tg[both]) / np.maximum(np.abs(ch["t_birth"][both]), T)
+    Kg, dirg = kinetic_mev([u[fg] for u in ug]), ug[2][fg] > 0
+    ref = O.push(OL, tg, *gx, K)
+    Kop, dirop = kinetic_mev([u[fg] for u in ref[:3]]), ref[2][fg] > 0
+    Kx_all, atoms, _, _ = load("rp_ne_fp64_1m_head")
+    Kx = Kx_all[0][:na].ravel()
+    assert np.array_equal(np.isfinite(Kx), fo)
+    v = parity.fp64_energy_verdict(Kg, dirg, Kop, dirop, Kx=Kx[fg], Koc=ch["K"][fg])
+    out = dict(electrons=int(fg.sum()), born_mismatch=int((fo != fg).sum()),
+               birth_time_max_rel=float(dt_rel.max()) if dt_rel.size else 0.0,
+               energy_rule=v, raw_chain_frac_le_1e8=float(parity.within(Kg, ch["K"][fg]).mean()),
+               note="energy_rule: oracle/parity.py -- GPU vs the double oracle's push of the "
+                    "same inputs, GPU vs the extended-precision oracle (every electron), "
+                    "directions; raw_chain = GPU chain vs the double oracle's own chain")
+    if mixed_out is not None:
+        um = [o[:n].cpu().numpy() for o in mixed_out[:3]]
+        Km = kinetic_mev([u[fg] for u in um])
+        rel = np.abs(Km - Kx[fg]) / Kx[fg]
+        out["mixed_vs_extended"] = dict(
+            frac_rel_err_le_1e3=float(np.mean(rel <= 1e-3)), median_rel_err=float(np.median(rel)),
+            mean_energy_rel_err=float(Km.mean() / Kx[fg].mean() - 1),
+            hist_decades_from_1e17=np.histogram(np.log10(np.maximum(rel, 1e-17)),
+                                                  bins=np.arange(-17, 2))[0].tolist())
+    return out
 
-    def kin(u):
-        u2 = u[0][both] ** 2 + u[1][both] ** 2 + u[2][both] ** 2
-        return 0.51099895 * u2 / (np.sqrt(1.0 + u2) + 1.0), u[2][both] > 0
 
-    Ko, dir_o = kin(out)
-    Kg, dir_g = kin(ug)
-    rel = np.abs(Kg - Ko) / Ko
-    ok = np.abs(Kg - Ko) <= 1e-8 * Ko + 1e-12
-    bad = np.nonzero(both)[0][~ok]
-    ill = 0
-    if bad.size:
-        tp = t[bad] + 1e-15 * np.maximum(np.abs(t[bad]), T)
-        xs, ys, zs = (np.repeat(a, K)[bad] for a in (x, y, z))
-        pert = O.push(OL, tp, xs, ys, zs, 1)
-        u2 = pert[0] ** 2 + pert[1] ** 2 + pert[2] ** 2
-        Kp = 0.51099895 * u2 / (np.sqrt(1.0 + u2) + 1.0)
-        ill = int((np.abs(Kp - Ko[~ok]) / Ko[~ok] > 1e-10).sum())
-    well = int(both.sum()) - ill
-    return dict(electrons=int(both.sum()), born_mismatch=int((fo != fg).sum()),
-                birth_time_max_rel=float(dt_rel.max()) if dt_rel.size else 0.0,
-                energy_frac_le_1e8=float(ok.mean()), energy_median_rel=float(np.median(rel)),
-                ill_conditioned=ill,
-                energy_frac_le_1e8_well_conditioned=float((ok.sum()) / max(well, 1)) if ill
-                else float(ok.mean()),
-                same_direction=float((dir_o == dir_g).mean()),
-                note="sample of the CPU baseline; ill-conditioned = the oracle's own energy "
-                     "moves by more than 1e-10 when the birth time moves by 1e-15 relative")
+def rel_err_histogram(rel):
+    """Electrons per decade of relative error, from 1e-17 to 10 (the first bin
+    also holds exact agreement), as a list of 18 counts."""
+    import torch
+    lg = torch.log10(rel.double().clamp(min=1e-17)).clamp(max=0.999)
+    return torch.histc(lg, bins=18, min=-17.0, max=1.0).long().cpu().tolist()
+
+
+def quantile_sorted(x, q):
+    """q-quantile of a 1-D tensor by sorting (any length)."""
+    v = x.double().sort().values
+    return float(v[min(v.numel() - 1, int(q * v.numel()))].item())
 
 
 def measure_mixed_workload(wl):
@@ -196,13 +242,16 @@ def measure_mixed_workload(wl):
                 mixed_electron_steps_per_s=steps / (msmx * 1e-3), speedup=ms64 / msmx,
                 frac_rel_err_le_1e3=float((rel <= 1e-3).double().mean().item()),
                 median_rel_err=float(rel.median().item()),
+                p99_rel_err=quantile_sorted(rel, 0.99),
                 mean_energy_rel_err=float((Kmx.double().mean() / K64.double().mean() - 1).item()),
-                same_direction=float((f64 == fmx).double().mean().item()))
+                same_direction=float((f64 == fmx).double().mean().item()),
+                rel_err_hist_decades_from_1e17=rel_err_histogram(rel))
 
 
-def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk):
-    """One timed batched sweep (after an untimed one that captures the graph)
-    on a side stream; electron-steps counted by the library."""
+def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk, chunks_total=None):
+    """One timed batched sweep on a side stream (its chunk sequence captured
+    into a hipGraph at the call and replayed per chunk; the capture is inside
+    the timed region); electron-steps counted by the library."""
     import torch
     from paper_2509_01741_amd import binding as B
     from paper_2509_01741_amd import pipeline
@@ -216,10 +265,9 @@ def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk):
                                                      wl["k_last"]), dtype=torch.uint8, device=dev)
     st = torch.cuda.Stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    g0 = B.rpdla_batched_graphs()
     with torch.cuda.stream(st):
-        pipeline.run_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk, stream=st, workspace=ws,
-                           counts=counts, tallies=tallies, electron_steps=steps)
-        counts.zero_(); tallies.zero_(); steps.zero_()
         a, b = ev(), ev()
         a.record(st)
         pipeline.run_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk, stream=st, workspace=ws,
@@ -230,9 +278,11 @@ def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk):
     n_steps = int(steps.sum().item())
     tal = tallies.sum(0).cpu().tolist()
     bwd = tallies[:, 1].double() / (tallies[:, 0] + tallies[:, 1]).clamp(min=1).double()
+    chunks = -(-atoms_per_cfg // atoms_per_chunk)
     return dict(workload=wl["name"], precision="mixed" if precision == B.RPDLA_MIXED else "f64",
                 configs=n_cfg, atoms_per_cfg=atoms_per_cfg, atoms_per_chunk=atoms_per_chunk,
-                chunks=-(-atoms_per_cfg // atoms_per_chunk), ms=round(ms, 2),
+                chunks_timed=chunks, chunks_total=chunks_total or chunks,
+                graph_captured=B.rpdla_batched_graphs() > g0, ms=round(ms, 2),
                 electron_steps=n_steps, electron_steps_per_s=n_steps / (ms * 1e-3),
                 born=int(tal[0] + tal[1]), backward_fraction_min_max=[float(bwd.min()), float(bwd.max())],
                 occupancy=occupancy(2, int(wl["field_order"]), precision))
@@ -334,66 +384,106 @@ def write_traffic_summary(fetch_dir, write_dir, atoms=1_000_000, copy_mib=512, s
     return rec
 
 
-def write_counter_summary(counter_dir, bench_json, out_json=PROFILE_COUNTERS_FILE):
-    """Turn the counter run (COUNTERS_CMD) and that run's bench line into
-    per-electron-step FLOPs and issue rates of the FP64 and mixed pushes, and
-    write out_json and the .md beside it."""
+def _per_dispatch(counter_dir):
+    """{form: {dispatch id: {counter: value summed over its dimensions}}}."""
     import csv
     import glob
-    per_dispatch = {}
+    per = {}
     for f in glob.glob(os.path.join(counter_dir, "**", "*counter_collection.csv"), recursive=True):
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                for form, name in (("fp64", "push_kernel<5, rpdla::ElecF64>"),
-                                   ("mixed", "push_kernel<5, rpdla::ElecMixed>")):
+                for form, name in COUNTER_KERNELS:
                     if name in r["Kernel_Name"] and "batch" not in r["Kernel_Name"]:
-                        d = per_dispatch.setdefault(form, {}).setdefault(int(r["Dispatch_Id"]), {})
+                        d = per.setdefault(form, {}).setdefault(int(r["Dispatch_Id"]), {})
                         d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return per
+
+
+def write_counter_summary(counter_dir, bench_json, counter_dir2=None, out_json=PROFILE_COUNTERS_FILE):
+    """Turn the counter runs (COUNTERS_CMD, and COUNTERS2_CMD into counter_dir2)
+    and the first run's bench line into per-unit FLOPs, issue rates, clock and
+    lane activity of the FP64 and mixed pushes and the ionization kernel, and
+    write out_json and the .md beside it."""
     # one launch per form: bench.py calls the mixed push twice (untimed, then
     # timed), so take the last dispatch of each kernel, the timed one
-    vals = {form: disp[max(disp)] for form, disp in per_dispatch.items()}
+    vals = {form: disp[max(disp)] for form, disp in _per_dispatch(counter_dir).items()}
+    vals2 = {}
+    if counter_dir2:
+        vals2 = {form: disp[max(disp)] for form, disp in _per_dispatch(counter_dir2).items()}
     line = [l for l in open(bench_json) if l.startswith("{")][-1]
     b = json.loads(line)
     steps = b["config"]["electron_steps"]
-    ms = {"fp64": b["roofline"]["push_ms"], "mixed": b["mixed"]["push_ms"]}
-    rec = dict(workload="rp_ne_fp64_1m at 1e5 atoms", electron_steps=steps,
+    atoms = b["config"]["atoms"]
+    ms = {"fp64": b["roofline"]["push_ms"], "mixed": b["mixed"]["push_ms"], "ionize": b["ionize_ms"]}
+    units = {"fp64": ("electron-step", steps), "mixed": ("electron-step", steps),
+             "ionize": ("atom", atoms)}
+    rec = dict(workload="rp_ne_fp64_1m at 1e5 atoms", electron_steps=steps, atoms=atoms,
                kernel_source_hash=kernel_source_hash(), command=COUNTERS_CMD,
-               summary_command=f"python3 bench.py --counters-from {counter_dir} BENCH_STDOUT")
-    md = ["# FP64 and mixed push counters, 1e5 atoms of the benchmark ensemble (states 1-10, order 5)",
-          "", "One counter run, then the summary (from the repository root, R=$GRAFT_REPO_ROOT):", "",
+               command2=COUNTERS2_CMD if counter_dir2 else None,
+               summary_command=f"python3 bench.py --counters-from {counter_dir} BENCH_STDOUT"
+                               + (f" {counter_dir2}" if counter_dir2 else ""))
+    forms = [f for f in ("fp64", "mixed", "ionize") if f in vals]
+    md = ["# Push and ionization counters, 1e5 atoms of the benchmark ensemble (states 1-10, order 5)",
+          "", "Two counter runs, then the summary (from the repository root, R=$GRAFT_REPO_ROOT):", "",
           "```", "cd /tmp && export TMPDIR=/tmp", COUNTERS_CMD + " > $R/gpurun_out/pmcS.json",
-          "cd $R && python3 bench.py --counters-from gpurun_out/pmcS gpurun_out/pmcS.json", "```",
-          "", f"{steps:.4e} electron-steps per push launch.", "",
-          "| counter (summed over the dispatch) | FP64 push | mixed push |", "|---|---|---|"]
+          COUNTERS2_CMD + " > $R/gpurun_out/pmcC.json",
+          "cd $R && python3 bench.py --counters-from gpurun_out/pmcS gpurun_out/pmcS.json gpurun_out/pmcC",
+          "```", "", f"{steps:.4e} electron-steps per push launch, {atoms} atoms per ionization launch.",
+          "", "| counter (summed over the dispatch) | " + " | ".join(forms) + " |",
+          "|---" * (len(forms) + 1) + "|"]
     for ctr in COUNTERS:
-        md.append(f"| {ctr} | {vals['fp64'].get(ctr, float('nan')):.4e} | "
-                  f"{vals['mixed'].get(ctr, float('nan')):.4e} |")
-    md += ["", "Derived (SQ counts are per wave instruction; a wave is 64 lanes):", ""]
-    for form in ("fp64", "mixed"):
-        v = vals[form]
+        md.append(f"| {ctr} | " + " | ".join(f"{vals[f].get(ctr, float('nan')):.4e}" for f in forms) + " |")
+    for ctr in COUNTERS2:
+        if vals2:
+            md.append(f"| {ctr} (second run) | "
+                      + " | ".join(f"{vals2.get(f, {}).get(ctr, float('nan')):.4e}" for f in forms) + " |")
+    md += ["", "Derived (SQ instruction counts are per wave instruction; a wave is 64 lanes):", ""]
+    for form in forms:
+        v, v2 = vals[form], vals2.get(form, {})
+        unit, n_units = units[form]
         f64 = 64 * v.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0)
         f32 = 64 * v.get("SQ_INSTS_VALU_FLOPS_FP32", 0.0)
         t = ms[form] * 1e-3
-        issue = v["SQ_INSTS_VALU"] / t / (256 * 2.4e9)
-        rec[form] = dict(push_ms=ms[form], fp64_flop_per_step=f64 / steps,
-                         fp32_flop_per_step=f32 / steps, valu_per_cu_cycle=issue,
-                         fp64_tflops=f64 / t / 1e12, fp32_tflops=f32 / t / 1e12,
-                         fp64_arith_frac=(v.get("SQ_INSTS_VALU_FMA_F64", 0) + v.get(
-                             "SQ_INSTS_VALU_MUL_F64", 0) + v.get("SQ_INSTS_VALU_ADD_F64", 0))
-                         / v["SQ_INSTS_VALU"])
-        r = rec[form]
-        md.append(f"- {form}: {r['fp64_flop_per_step']:.0f} FP64 + {r['fp32_flop_per_step']:.0f} "
-                  f"FP32 FLOPs per electron-step; {r['fp64_tflops']:.1f} TFLOP/s FP64 + "
-                  f"{r['fp32_tflops']:.1f} TFLOP/s FP32 in {ms[form]:.1f} ms; "
-                  f"{issue:.2f} VALU wave instructions per CU per cycle (256 CU x 2.4 GHz); "
-                  f"FP64 add/mul/fma are {100 * r['fp64_arith_frac']:.0f}% of VALU instructions.")
+        r = dict(ms=ms[form], unit=unit, fp64_flop_per_unit=f64 / n_units,
+                 fp32_flop_per_unit=f32 / n_units, fp64_tflops=f64 / t / 1e12,
+                 fp32_tflops=f32 / t / 1e12,
+                 valu_per_cu_cycle_at_2p4ghz=v["SQ_INSTS_VALU"] / t / (256 * 2.4e9),
+                 fp64_arith_frac=(v.get("SQ_INSTS_VALU_FMA_F64", 0) + v.get("SQ_INSTS_VALU_MUL_F64", 0)
+                                  + v.get("SQ_INSTS_VALU_ADD_F64", 0)) / v["SQ_INSTS_VALU"])
+        if form != "ionize":
+            r["fp64_flop_per_step"] = r["fp64_flop_per_unit"]
+            r["fp32_flop_per_step"] = r["fp32_flop_per_unit"]
+        if v2.get("GRBM_GUI_ACTIVE"):
+            # GRBM_GUI_ACTIVE is summed over the 8 XCDs: cycles of the dispatch
+            cyc = v2["GRBM_GUI_ACTIVE"] / 8.0
+            r["clock_ghz"] = cyc / t / 1e9
+            r["valu_per_cu_cycle"] = v2["SQ_INSTS_VALU"] / (256 * cyc)
+            r["salu_per_valu"] = v2.get("SQ_INSTS_SALU", 0.0) / v2["SQ_INSTS_VALU"]
+            if v2.get("SQ_ACTIVE_INST_VALU"):
+                r["active_lanes_per_valu_cycle"] = (v2.get("SQ_THREAD_CYCLES_VALU", 0.0)
+                                                    / v2["SQ_ACTIVE_INST_VALU"])
+        else:
+            r["valu_per_cu_cycle"] = r["valu_per_cu_cycle_at_2p4ghz"]
+        rec[form] = r
+        line = (f"- {form}: {r['fp64_flop_per_unit']:.0f} FP64 + {r['fp32_flop_per_unit']:.0f} FP32 "
+                f"FLOPs per {unit}; {r['fp64_tflops']:.1f} TFLOP/s FP64 + {r['fp32_tflops']:.1f} "
+                f"TFLOP/s FP32 in {ms[form]:.1f} ms; FP64 add/mul/fma are "
+                f"{100 * r['fp64_arith_frac']:.0f}% of VALU instructions")
+        if "clock_ghz" in r:
+            line += (f"; clock {r['clock_ghz']:.2f} GHz (GRBM_GUI_ACTIVE / 8 XCDs over the launch), "
+                     f"{r['valu_per_cu_cycle']:.2f} VALU wave instructions per CU per measured cycle, "
+                     f"{r['salu_per_valu']:.2f} SALU per VALU instruction")
+            if "active_lanes_per_valu_cycle" in r:
+                line += (f", {r['active_lanes_per_valu_cycle']:.1f} active lanes per wave-cycle of VALU "
+                         "work (SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU)")
+        md.append(line + ".")
     md += ["", "A wave64 FP64 instruction occupies its SIMD for 4 cycles, and so does an unpacked FP32",
            "one (the kernels are compiled without packed FP32), so the ceiling is 1.0 wave",
            "instruction per CU per cycle for both forms: 78.6 TFLOP/s of FMAs in either precision.",
            "The published 157.3 TFLOP/s FP32 peak counts packed FP32 FMAs.  The counters are taken",
-           "from one launch per form: the timed one, the last of each kernel in the run.", "",
+           "from one launch per kernel: the timed one, the last of each kernel in the run.", "",
            f"Kernel source hash {kernel_source_hash()} (bench.py uses these figures only for",
-           "that build of the push kernels)."]
+           "that build of the kernels)."]
     with open(out_json, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
@@ -412,6 +502,71 @@ def occupancy(kind, field, precision):
         return None
 
 
+KSTATS_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/ktrace -o run "
+              "-- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline")
+PROFILE_KSTATS_FILE = os.path.join(ROOT, "profiles", "push_fp64_rp_ne_fp64_1m_kernel_stats.md")
+
+
+def write_kernel_stats_summary(trace_dir, bench_json, out_md=PROFILE_KSTATS_FILE):
+    """Turn the kernel-trace statistics of one bench run (KSTATS_CMD) into the
+    kernel-time table, with bench.py's own HIP-event times of the same run."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
+    rows = list(csv.DictReader(open(files[0])))
+    line = [l for l in open(bench_json) if l.startswith("{")][-1]
+    b = json.loads(line)
+    md = ["# Kernel time, FP64 full ensemble (1e6 atoms, states 1-10, order-5 field), the mixed and",
+          "# controlled-step pushes of the same slots, and the batched sweeps", "",
+          "Command (on the MI355X box, from the repository root, R=$GRAFT_REPO_ROOT), then the summary:",
+          "", "```", "cd /tmp && export TMPDIR=/tmp", KSTATS_CMD + " > $R/gpurun_out/ktrace.json",
+          "cd $R && python3 bench.py --kernel-stats-from gpurun_out/ktrace gpurun_out/ktrace.json",
+          "```", "", "`run_kernel_stats.csv`, kernels above 0.01% of GPU time (durations in ms):", "",
+          "| kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|"]
+    push_avg = None
+    for r in rows:
+        pct = float(r["Percentage"])
+        if pct < 0.01:
+            continue
+        name = r["Name"]
+        avg = float(r["AverageNs"]) / 1e6
+        if name.endswith("push_kernel<5, rpdla::ElecF64>") and "batch" not in name:
+            push_avg = avg
+        md.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | {avg:.2f} | "
+                  f"{pct:.2f} |")
+    md += ["", f"The single-configuration FP64 push (`push_kernel<5, ElecF64>`, one launch over the "
+           f"{b['config']['slots']:.0e} slots of the benchmark step) averages "
+           f"{push_avg if push_avg is not None else float('nan'):.2f} ms here; bench.py's own HIP-event "
+           f"time for the same launch in the same profiled run is {b['roofline']['push_ms']:.2f} ms "
+           f"(`push_ms`), and its ionization launch {b['ionize_ms']:.2f} ms (`ionize_ms`).",
+           "The batched kernels belong to the sweeps bench.py also times (64 configurations in FP64 "
+           "and mixed precision, 16 large configurations in mixed precision); `push_kernel<5, ElecDP>` "
+           "is the controlled-step push of the same slots."]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+def ionize_roofline(atoms, ion_ms):
+    """Roofline object of the ionization kernel: its FP64 FLOPs per atom come
+    from the counter run (the work is data-dependent: panels are skipped where
+    the rate bound vanishes, and the Newton iterations vary), taken on the
+    same ensemble at 1e5 atoms, times this launch's atoms over its time."""
+    crec = _counter_record()
+    if crec is None or "ionize" not in crec:
+        return None
+    r = crec["ionize"]
+    ach = r["fp64_flop_per_unit"] * atoms / (ion_ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": "ionize_kernel<5>", "achieved": ach,
+            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None, "flop_per_atom": r["fp64_flop_per_unit"],
+            "flop_source": "executed FP64 FLOPs per atom, counter run at 1e5 atoms of this ensemble",
+            "valu_per_cu_cycle": r.get("valu_per_cu_cycle"),
+            "active_lanes_per_valu_cycle": r.get("active_lanes_per_valu_cycle")}
+
+
 def _counter_record():
     try:
         rec = json.load(open(PROFILE_COUNTERS_FILE))
@@ -424,8 +579,11 @@ def main():
     if len(sys.argv) == 4 and sys.argv[1] == "--traffic-from":
         write_traffic_summary(sys.argv[2], sys.argv[3])
         return
-    if len(sys.argv) == 4 and sys.argv[1] == "--counters-from":
-        write_counter_summary(sys.argv[2], sys.argv[3])
+    if len(sys.argv) == 4 and sys.argv[1] == "--kernel-stats-from":
+        write_kernel_stats_summary(sys.argv[2], sys.argv[3])
+        return
+    if len(sys.argv) in (4, 5) and sys.argv[1] == "--counters-from":
+        write_counter_summary(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) == 5 else None)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,8 +671,10 @@ def main():
             traffic = None
 
     mixed = None
+    mixed_outs = None
     if not args.no_mixed:
         outs = tuple(torch.empty_like(o) for o in ens.out)
+        mixed_outs = outs
         B.rpdla_push(ens.L, B.RPDLA_MIXED, ens.tb, ens.x, ens.y, ens.z, ens.K, outs)
         torch.cuda.synchronize()
         a, b = ev(), ev()
@@ -538,7 +698,8 @@ def main():
             speedup_vs_fp64=push_avg / mix_ms,
             frac_rel_err_le_1e3=float((rel <= 1e-3).double().mean().item()),
             median_rel_err=float(rel.median().item()),
-            p99_rel_err=float(torch.quantile(rel[:1_000_000].double(), 0.99).item()),
+            p99_rel_err=quantile_sorted(rel, 0.99),
+            rel_err_hist_decades_from_1e17=rel_err_histogram(rel),
             mean_energy_rel_err=float((Kmx.double().mean() / K64.double().mean() - 1).item()),
             same_direction=float((f64 == fmx).double().mean().item()),
         )
@@ -605,13 +766,16 @@ def main():
     batched = None
     if not args.no_batched:
         batched = {}
-        r = measure_sweep(workloads.SWEEP_FP64, B.RPDLA_FP64, 16384, 16384)
+        sw = workloads.SWEEP_FP64
+        r = measure_sweep(sw, B.RPDLA_FP64, sw["atoms"], sw["atoms"])
         log(f"batched sweep FP64: {r}")
         batched["sweep64_fp64"] = r
-        r = measure_sweep(workloads.SWEEP_FP64, B.RPDLA_MIXED, 16384, 16384)
+        r = measure_sweep(sw, B.RPDLA_MIXED, sw["atoms"], sw["atoms"])
         log(f"batched sweep mixed: {r}")
         batched["sweep64_mixed"] = r
-        r = measure_sweep(workloads.LARGE_MIXED, B.RPDLA_MIXED, 100_000, 50_000)
+        lg = workloads.LARGE_MIXED
+        r = measure_sweep(lg, B.RPDLA_MIXED, lg["chunk"], lg["chunk"],
+                          chunks_total=-(-lg["atoms"] // lg["chunk"]))
         log(f"large mixed sweep: {r}")
         batched["large16_mixed"] = r
 
@@ -619,7 +783,7 @@ def main():
     parity = None
     if not args.no_cpu_baseline:
         try:
-            base, parity = cpu_baseline(ens)
+            base, parity = cpu_baseline(ens, mixed_outs)
             log(f"cpu baseline: {base['value']:.3e} e-steps/s on {base['cores']} threads")
             log(f"FP64 vs oracle: {parity}")
         except Exception as e:  # the oracle is a reported baseline only
@@ -662,6 +826,7 @@ def main():
         },
         "push_electron_steps_per_s": push_rate,
         "ionize_ms": round(ion_avg, 2),
+        "ionize": ionize_roofline(ens.n, ion_avg),
         "tallies": dict(zip(["fwd", "bwd", "below", "above", "unborn", "nan"], tal)),
         "mixed": mixed,
         "adaptive": adaptive,
