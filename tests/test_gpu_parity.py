@@ -205,10 +205,12 @@ def test_push_plane_wave_parity(env):
 
 def test_mixed_vs_fp64(env):
     """Mixed form against the FP64 form on the same slots: per-electron
-    |dK|/K <= 1e-3 for the large majority and the ensemble mean within 0.1%."""
+    |dK|/K <= 1e-3 for the large majority and the ensemble mean within 0.1%.
+    The ensemble is ~3.5e4 electrons: on a few thousand, one ill-conditioned
+    electron of ~100 MeV off by a few percent moves the mean by 0.1% alone."""
     torch, B, O = env
     L, _ = _lasers(B, O, 5)
-    n, K = 400, 10
+    n, K = 4000, 10
     x, y, z = B.rpdla_sample_atoms(0, 9, 0, n, 2 * L.w0, B.rpdla_rayleigh(L))
     tb = B.rpdla_ionize(L, 0, 9, 0, x, y, z, 1, K)
     a = [o.cpu().numpy() for o in B.rpdla_push(L, 0, tb, x, y, z, K)]
