@@ -30,13 +30,13 @@ C_LIGHT = 299792458.0
 # the hardware reciprocal / reciprocal-square-root estimates = 1 FLOP,
 # fma = 2; the sine/cosine, exponential, reciprocal and reciprocal square root
 # at the operations of their polynomial and Newton sequences).  Per
-# right-hand side: field 191 (position terms 8, reciprocal 9, phase and
-# envelope arguments 7, exponential 29, sine/cosine of the two-part phase 43,
+# right-hand side: field 186 (position terms 8, reciprocal 7, phase and
+# envelope arguments 7, exponential 29, sine/cosine of the two-part phase 40,
 # amplitude 5, w-recurrence 30, brackets 57, radial and axial scales 3) +
-# Lorentz 30 (gamma 18, velocity 3, force from the radial parts 9); per step
-# 4 x 221 + RK4 115 (stage arguments 48, slope sums 24, increments 15,
-# compensated sums of the seven state variables 28) = 999.
-ALGO_FLOP_PER_STEP = 999.0
+# Lorentz 27 (gamma 15, velocity 3, force from the radial parts 9); per step
+# 4 x 213 + RK4 115 (stage arguments 48, slope sums 24, increments 15,
+# compensated sums of the seven state variables 28) = 967.
+ALGO_FLOP_PER_STEP = 967.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # Published FP32 vector peak.  It counts packed FP32 FMAs (two per lane per
 # instruction); the kernels are compiled without packed FP32, so an FP32
