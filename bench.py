@@ -38,12 +38,10 @@ C_LIGHT = 299792458.0
 # compensated sums of the seven state variables 28) = 967.
 ALGO_FLOP_PER_STEP = 967.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
-# Published FP32 vector peak.  It counts packed FP32 FMAs (two per lane per
-# instruction); the kernels are compiled without packed FP32, so an FP32
-# instruction, like an FP64 one, occupies its SIMD for 4 cycles per wave64 and
-# the ceiling for their unpacked FP32 FMAs is the FP64 figure, 78.6 TFLOP/s.
+# Published FP32 vector peak (it counts packed FP32 FMAs; the kernels are
+# compiled without packed FP32).
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-PROFILE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "push_rp_ne_fp64_100k_counters.json")
+PROFILE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "push_ionize_rp_ne_fp64_1m_counters.json")
 # two counter passes (one rocprofv3 run each): instruction and FLOP counts,
 # then cycles, issue and lane activity
 COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32",
@@ -52,8 +50,8 @@ COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_V
 COUNTERS2 = ["GRBM_GUI_ACTIVE", "GRBM_COUNT", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_BUSY_CU_CYCLES",
              "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"]
 COUNTERS_RUN = ("rocprofv3 --pmc {ctrs} --output-format csv -d $R/gpurun_out/{d} -o run -- python3 "
-                "$R/bench.py --steps 1 --warmup 0 --atoms 100000 --no-cpu-baseline --no-adaptive "
-                "--no-batched")
+                "$R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-adaptive --no-batched "
+                "--no-mixed-workload")
 COUNTERS_CMD = COUNTERS_RUN.format(ctrs=" ".join(COUNTERS), d="pmcS")
 COUNTERS2_CMD = COUNTERS_RUN.format(ctrs=" ".join(COUNTERS2), d="pmcC")
 COUNTER_KERNELS = (("fp64", "push_kernel<5, rpdla::ElecF64>"),
@@ -417,13 +415,13 @@ def write_counter_summary(counter_dir, bench_json, counter_dir2=None, out_json=P
     ms = {"fp64": b["roofline"]["push_ms"], "mixed": b["mixed"]["push_ms"], "ionize": b["ionize_ms"]}
     units = {"fp64": ("electron-step", steps), "mixed": ("electron-step", steps),
              "ionize": ("atom", atoms)}
-    rec = dict(workload="rp_ne_fp64_1m at 1e5 atoms", electron_steps=steps, atoms=atoms,
+    rec = dict(workload="rp_ne_fp64_1m", electron_steps=steps, atoms=atoms,
                kernel_source_hash=kernel_source_hash(), command=COUNTERS_CMD,
                command2=COUNTERS2_CMD if counter_dir2 else None,
                summary_command=f"python3 bench.py --counters-from {counter_dir} BENCH_STDOUT"
                                + (f" {counter_dir2}" if counter_dir2 else ""))
     forms = [f for f in ("fp64", "mixed", "ionize") if f in vals]
-    md = ["# Push and ionization counters, 1e5 atoms of the benchmark ensemble (states 1-10, order 5)",
+    md = ["# Push and ionization counters, benchmark ensemble (1e6 atoms, states 1-10, order 5)",
           "", "Two counter runs, then the summary (from the repository root, R=$GRAFT_REPO_ROOT):", "",
           "```", "cd /tmp && export TMPDIR=/tmp", COUNTERS_CMD + " > $R/gpurun_out/pmcS.json",
           COUNTERS2_CMD + " > $R/gpurun_out/pmcC.json",
@@ -477,11 +475,14 @@ def write_counter_summary(counter_dir, bench_json, counter_dir2=None, out_json=P
                 line += (f", {r['active_lanes_per_valu_cycle']:.1f} active lanes per wave-cycle of VALU "
                          "work (SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU)")
         md.append(line + ".")
-    md += ["", "A wave64 FP64 instruction occupies its SIMD for 4 cycles, and so does an unpacked FP32",
-           "one (the kernels are compiled without packed FP32), so the ceiling is 1.0 wave",
-           "instruction per CU per cycle for both forms: 78.6 TFLOP/s of FMAs in either precision.",
-           "The published 157.3 TFLOP/s FP32 peak counts packed FP32 FMAs.  The counters are taken",
-           "from one launch per kernel: the timed one, the last of each kernel in the run.", "",
+    md += ["", "A wave64 FP64 instruction occupies its SIMD for 4 cycles: the FP64 ceiling is 1.0 wave",
+           "instruction per CU per cycle (78.6 TFLOP/s of FMAs at 2.4 GHz).  The mixed push issues",
+           "more than that, so its FP32 instructions do not hold their SIMD for 4 cycles each; it is",
+           "set against the published peaks (157.3 TFLOP/s FP32, counted with packed FMAs, which the",
+           "kernels do not use).  FLOPs per unit count every lane of a wave instruction (SQ counts",
+           "are per wave); the active-lane figure gives the share of lanes doing work.  The counters",
+           "are taken from one launch per kernel: the timed one, the last of each kernel in the run.",
+           "",
            f"Kernel source hash {kernel_source_hash()} (bench.py uses these figures only for",
            "that build of the kernels)."]
     with open(out_json, "w") as fh:
@@ -507,15 +508,26 @@ KSTATS_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun
 PROFILE_KSTATS_FILE = os.path.join(ROOT, "profiles", "push_fp64_rp_ne_fp64_1m_kernel_stats.md")
 
 
+def _short_kernel_name(name):
+    """Kernel name without its argument list (and shortened if still long)."""
+    head = name.split("(", 1)[0]
+    return head if len(head) <= 80 else head[:77] + "..."
+
+
 def write_kernel_stats_summary(trace_dir, bench_json, out_md=PROFILE_KSTATS_FILE):
     """Turn the kernel-trace statistics of one bench run (KSTATS_CMD) into the
-    kernel-time table, with bench.py's own HIP-event times of the same run."""
+    kernel-time table, with the benchmark step's own dispatches set against
+    bench.py's HIP-event times of the same run."""
     import csv
     import glob
-    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
-    if not files:
-        raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
-    rows = list(csv.DictReader(open(files[0])))
+
+    def one(pattern):
+        files = glob.glob(os.path.join(trace_dir, "**", pattern), recursive=True)
+        if not files:
+            raise SystemExit(f"no {pattern} under {trace_dir}")
+        return list(csv.DictReader(open(files[0])))
+
+    stats, trace = one("*kernel_stats.csv"), one("*kernel_trace.csv")
     line = [l for l in open(bench_json) if l.startswith("{")][-1]
     b = json.loads(line)
     md = ["# Kernel time, FP64 full ensemble (1e6 atoms, states 1-10, order-5 field), the mixed and",
@@ -525,25 +537,31 @@ def write_kernel_stats_summary(trace_dir, bench_json, out_md=PROFILE_KSTATS_FILE
           "cd $R && python3 bench.py --kernel-stats-from gpurun_out/ktrace gpurun_out/ktrace.json",
           "```", "", "`run_kernel_stats.csv`, kernels above 0.01% of GPU time (durations in ms):", "",
           "| kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|"]
-    push_avg = None
-    for r in rows:
+    for r in stats:
         pct = float(r["Percentage"])
         if pct < 0.01:
             continue
-        name = r["Name"]
-        avg = float(r["AverageNs"]) / 1e6
-        if name.endswith("push_kernel<5, rpdla::ElecF64>") and "batch" not in name:
-            push_avg = avg
-        md.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | {avg:.2f} | "
-                  f"{pct:.2f} |")
-    md += ["", f"The single-configuration FP64 push (`push_kernel<5, ElecF64>`, one launch over the "
-           f"{b['config']['slots']:.0e} slots of the benchmark step) averages "
-           f"{push_avg if push_avg is not None else float('nan'):.2f} ms here; bench.py's own HIP-event "
-           f"time for the same launch in the same profiled run is {b['roofline']['push_ms']:.2f} ms "
-           f"(`push_ms`), and its ionization launch {b['ionize_ms']:.2f} ms (`ionize_ms`).",
-           "The batched kernels belong to the sweeps bench.py also times (64 configurations in FP64 "
-           "and mixed precision, 16 large configurations in mixed precision); `push_kernel<5, ElecDP>` "
-           "is the controlled-step push of the same slots."]
+        md.append(f"| `{_short_kernel_name(r['Name'])}` | {r['Calls']} | "
+                  f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['AverageNs']) / 1e6:.2f} | {pct:.2f} |")
+    # the benchmark step is the first ionization and the first FP64 push dispatch
+    # (one timed step, no warm-up); later ones belong to the mixed workload
+    first = {}
+    for r in sorted(trace, key=lambda r: int(r["Dispatch_Id"])):
+        for key, pat in (("ionize", "rpdla::ionize_kernel<5>("),
+                         ("push", "rpdla::push_kernel<5, rpdla::ElecF64>(")):
+            if pat in r["Kernel_Name"] and key not in first:
+                first[key] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    md += ["", "The benchmark step's dispatches in `run_kernel_trace.csv` against bench.py's own "
+           "HIP-event times of the same profiled run:", "",
+           "| kernel | trace ms | bench.py ms |", "|---|---|---|",
+           f"| `push_kernel<5, ElecF64>` (1e7 slots) | {first.get('push', float('nan')):.2f} | "
+           f"{b['roofline']['push_ms']:.2f} (`push_ms`) |",
+           f"| `ionize_kernel<5>` (1e6 atoms) | {first.get('ionize', float('nan')):.2f} | "
+           f"{b['ionize_ms']:.2f} (`ionize_ms`) |", "",
+           "The second call of each is the FP64 reference of the mixed workload (`rp_ne_mixed_1m`); "
+           "the batched kernels belong to the sweeps bench.py also times (64 configurations in FP64 "
+           "and mixed precision, 16 large configurations in mixed precision); `push_kernel<5, "
+           "ElecDP>` is the controlled-step push of the benchmark slots."]
     with open(out_md, "w") as fh:
         fh.write("\n".join(md) + "\n")
     print("\n".join(md))
@@ -594,6 +612,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mixed-workload", action="store_true",
+                    help="skip the mixed form's own workload (counter runs read the last launches)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -713,18 +733,17 @@ def main():
                 "peak_fp32": FP32_VECTOR_PEAK_TFLOPS, "peak_fp64": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s",
                 "frac": f32 / FP32_VECTOR_PEAK_TFLOPS + f64m / FP64_VECTOR_PEAK_TFLOPS,
-                "frac_unpacked_ceiling": (f32 + f64m) / FP64_VECTOR_PEAK_TFLOPS,
                 "flop_per_electron_step": {"fp32": crec["mixed"]["fp32_flop_per_step"],
                                            "fp64": crec["mixed"]["fp64_flop_per_step"]},
                 "valu_per_cu_cycle": crec["mixed"]["valu_per_cu_cycle"],
+                "clock_ghz": crec["mixed"].get("clock_ghz"),
                 "note": "frac = FP32 share of the published FP32 vector peak (packed FMAs) + "
-                        "FP64 share of the FP64 vector peak; frac_unpacked_ceiling = both "
-                        "against 78.6 TFLOP/s, the ceiling of unpacked FP32 and FP64 FMAs, "
-                        "which share the SIMDs at 4 cycles per wave64 instruction"}
+                        "FP64 share of the FP64 vector peak; FLOPs per electron-step from the "
+                        "counter run (executed, every lane of a wave instruction counted)"}
         mixed["occupancy"] = occupancy(0, int(ens.L.field), B.RPDLA_MIXED)
         log(f"mixed: {mixed}")
 
-    if mixed is not None and args.atoms is None:
+    if mixed is not None and args.atoms is None and not args.no_mixed_workload:
         # full-size runs only: counter runs at a reduced size read the last
         # push launches, which must stay those of the benchmark ensemble
         mixed["workload_1pw"] = measure_mixed_workload(workloads.MIXED_AB)
