@@ -163,8 +163,12 @@ rpdla_status rpdla_sample_atoms_annulus(uint64_t seed, uint32_t cfg_id, uint64_t
  * potentials, w = 0 where ln w[1/s] < -700.
  * t_birth: device double[n_atoms * K], K = k_last - k_first + 1, atom-major
  * (slot j*K + (k - k_first)), seconds, +INF where the state is not reached
- * in the window.  EINVAL: bad laser, 1 <= k_first <= k_last <= 10 violated,
- * null pointers with n_atoms > 0.
+ * in the window.  From 16384 atoms on, the atoms are taken in an order that
+ * groups similar work in each wave (a sort by their peak-field bound), which
+ * needs stream-ordered scratch of about 16 bytes per atom (hipMallocAsync /
+ * hipFreeAsync on `stream`); results do not depend on the order.  EINVAL: bad
+ * laser, 1 <= k_first <= k_last <= 10 violated, null pointers with
+ * n_atoms > 0.
  * ------------------------------------------------------------------------ */
 rpdla_status rpdla_ionize(const rpdla_laser* L, uint64_t seed, uint32_t cfg_id,
                           uint64_t first_atom, int64_t n_atoms, const double* x,

@@ -2,6 +2,7 @@
 // argument validation, the per-configuration constants in normalized units,
 // kernel dispatch and launch shapes.
 #include <hip/hip_runtime.h>
+#include <hipcub/device/device_radix_sort.hpp>
 
 #include <math.h>
 #include <stdarg.h>
@@ -52,6 +53,11 @@ constexpr double kNeIpEv[10] = {21.564540, 40.96297, 63.4233, 97.1900, 126.247,
 
 // Largest slot count of one push call.
 constexpr int64_t kMaxPushSlots = (int64_t)1 << 40;
+// Below this many atoms the ionization runs in the caller's order (sorting
+// the atoms by work would cost more than it saves).
+constexpr int64_t kIonizeSortMin = 16384;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 thread_local std::string g_err;
 
@@ -228,9 +234,43 @@ rpdla_status launch_ionize(const DevCfg& c, uint64_t seed, uint32_t cfg, uint64_
                            int kl, double* tb, hipStream_t st)
 {
     const int bs = get_shape(kKindIonize, FIELD, 0).block;
-    hipLaunchKernelGGL(rpdla::ionize_kernel<FIELD>, dim3((unsigned)cdiv(n, bs)), dim3(bs), 0, st,
-                       c, seed, cfg, first, n, x, y, z, kf, kl, tb);
-    RPDLA_HIP(hipGetLastError());
+    if (n < kIonizeSortMin || n > (int64_t)INT32_MAX) {
+        hipLaunchKernelGGL(rpdla::ionize_kernel<FIELD>, dim3((unsigned)cdiv(n, bs)), dim3(bs), 0,
+                           st, c, seed, cfg, first, n, x, y, z, kf, kl, tb,
+                           (const uint32_t*)nullptr);
+        RPDLA_HIP(hipGetLastError());
+        return RPDLA_OK;
+    }
+    // atoms ordered by their work key (radix sort of key/index pairs), so that
+    // each wave holds atoms of similar work; stream-ordered scratch
+    size_t sort_bytes = 0;
+    RPDLA_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t*)nullptr,
+                                                 (uint32_t*)nullptr, (const uint32_t*)nullptr,
+                                                 (uint32_t*)nullptr, (int)n, 0, 32, st));
+    const size_t arr = align256((size_t)n * sizeof(uint32_t));
+    char* buf = nullptr;
+    RPDLA_HIP(hipMallocAsync((void**)&buf, 4 * arr + sort_bytes, st));
+    uint32_t* key_in = (uint32_t*)buf;
+    uint32_t* key_out = (uint32_t*)(buf + arr);
+    uint32_t* idx_in = (uint32_t*)(buf + 2 * arr);
+    uint32_t* idx_out = (uint32_t*)(buf + 3 * arr);
+    rpdla_status r = RPDLA_OK;
+    hipLaunchKernelGGL(rpdla::ionize_key_kernel<FIELD>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0,
+                       st, c, n, x, y, z, key_in, idx_in);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(buf + 4 * arr, sort_bytes, key_in, key_out, idx_in,
+                                               idx_out, (int)n, 0, 32, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(rpdla::ionize_kernel<FIELD>, dim3((unsigned)cdiv(n, bs)), dim3(bs), 0,
+                           st, c, seed, cfg, first, n, x, y, z, kf, kl, tb,
+                           (const uint32_t*)idx_out);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) r = fail(RPDLA_EHIP, "ionize: %s", hipGetErrorString(e));
+    const hipError_t fe = hipFreeAsync(buf, st);
+    if (r != RPDLA_OK) return r;
+    if (fe != hipSuccess) return fail(RPDLA_EHIP, "hipFreeAsync: %s", hipGetErrorString(fe));
     return RPDLA_OK;
 }
 
@@ -655,7 +695,6 @@ rpdla_status rpdla_histogram(int64_t n, const double* t_birth, const double* ux,
 // ===========================================================================
 namespace {
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
     size_t cfg, geo, ctl, x, y, z, tb, ux, uy, uz, total;

@@ -292,17 +292,39 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
     }
 }
 
+// Lane i ionizes atom order[i] (atom i without an order).  An order that
+// groups atoms of similar work in the same wave keeps the lanes of a wave
+// busy for the same number of panels; the results do not depend on it.
 template <int FIELD>
 __global__ void __launch_bounds__(256, 3) ionize_kernel(
     DevCfg c, uint64_t seed, uint32_t cfg, uint64_t first_atom, int64_t n,
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    int k_first, int k_last, double* __restrict__ t_birth)
+    int k_first, int k_last, double* __restrict__ t_birth, const uint32_t* __restrict__ order)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t a = order ? (int64_t)order[i] : i;
     const int K = k_last - k_first + 1;
-    ionize_atom<FIELD>(c, seed, cfg, first_atom + (uint64_t)i, x[i] * c.k, y[i] * c.k,
-                       z[i] * c.k, k_first, K, t_birth + i * K);
+    ionize_atom<FIELD>(c, seed, cfg, first_atom + (uint64_t)a, x[a] * c.k, y[a] * c.k,
+                       z[a] * c.k, k_first, K, t_birth + a * K);
+}
+
+// Work key of each atom for that order: the bound of its peak |a|^2 (the
+// states' windows, and so the panels an atom integrates, grow with it), as
+// the bit pattern of a non-negative float, which orders like the value.
+template <int FIELD>
+__global__ void __launch_bounds__(256) ionize_key_kernel(DevCfg c, int64_t n,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ y,
+                                                         const double* __restrict__ z,
+                                                         uint32_t* __restrict__ key,
+                                                         uint32_t* __restrict__ idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float b2 = (float)bound2_f64<FIELD>(c, x[i] * c.k, y[i] * c.k, z[i] * c.k);
+    key[i] = __float_as_uint(b2 > 0.0f ? b2 : 0.0f);
+    idx[i] = (uint32_t)i;
 }
 
 // ---------------------------------------------------------------------------
