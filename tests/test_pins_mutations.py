@@ -143,8 +143,8 @@ def _mutate(src, old, new, nth):
     return src[:pos] + new + src[pos + len(old):]
 
 
-def _run_pins(lib_path, timeout=600):
-    env = dict(os.environ, RPDLA_ORACLE_LIB=lib_path, OMP_NUM_THREADS="2")
+def _run_pins(lib_path, timeout=600, threads=2):
+    env = dict(os.environ, RPDLA_ORACLE_LIB=lib_path, OMP_NUM_THREADS=str(threads))
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] + PIN_FILES
     r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=timeout)
     return r.returncode, r.stdout[-400:]
@@ -195,5 +195,6 @@ def test_pins_hold_for_extended_build():
     same pins as the plain build."""
     import oracle
     oracle.build(force=False)
-    rc, out = _run_pins(os.path.join(ROOT, "oracle", "liborc_ext.so"), timeout=900)
+    rc, out = _run_pins(os.path.join(ROOT, "oracle", "liborc_ext.so"), timeout=900,
+                        threads=os.cpu_count() or 2)
     assert rc == 0, out
