@@ -840,6 +840,15 @@ def main():
             # kernel's registers and resident waves, HBM rate from the traffic
             "valu_per_cu_cycle": (None if _counter_record() is None else
                                   _counter_record()["fp64"]["valu_per_cu_cycle"]),
+            # the clock the counter run measured under this load, and the
+            # fraction of the FP64 peak at that clock (the published peak
+            # assumes 2.4 GHz)
+            "clock_ghz_counters": (None if _counter_record() is None else
+                                   _counter_record()["fp64"].get("clock_ghz")),
+            "frac_at_measured_clock": (
+                None if _counter_record() is None or not _counter_record()["fp64"].get("clock_ghz")
+                else achieved_tflops / (FP64_VECTOR_PEAK_TFLOPS
+                                        * _counter_record()["fp64"]["clock_ghz"] / 2.4)),
             "occupancy": occupancy(0, int(ens.L.field), B.RPDLA_FP64),
             "hbm_gb_s": None if traffic is None else traffic / (push_avg * 1e-3) / 1e9,
         },

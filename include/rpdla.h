@@ -344,8 +344,8 @@ rpdla_status rpdla_histogram2d(int64_t n, const double* a, const double* b, cons
  * configuration; each chunk runs sample -> ionize -> push -> histogram, the
  * push as ONE persistent launch over every configuration's electrons: every
  * configuration has its own work counter, each wave serves one configuration
- * at a time (its constants copied from an LDS table into scalar registers)
- * and moves to another with work left when its own runs dry; lanes are
+ * at a time (its constants read with scalar loads from the configuration
+ * table) and moves to another with work left when its own runs dry; lanes are
  * refilled as their electron finishes.
  * On a non-null stream that is not being captured, the chunk's launch
  * sequence is captured once in a hipGraph (the chunk index advances in device
@@ -421,7 +421,9 @@ rpdla_status rpdla_get_launch_shape(int32_t kernel, int32_t field, int32_t preci
  * private scratch bytes per lane (*scratch_bytes, nonzero only when registers
  * spill) and resident waves per SIMD (*waves_per_simd, from the runtime's
  * occupancy query; a CU has four SIMDs).  The batched push is sized with the
- * LDS table of 64 configurations.  Host pointers, all non-NULL; RPDLA_EINVAL
+ * per-configuration step counters of 64 configurations in LDS.  Field 21, 23
+ * or 25 (linear focus) is accepted for the FP64 forms.  Host pointers, all
+ * non-NULL; RPDLA_EINVAL
  * otherwise, RPDLA_EHIP when the runtime query fails. */
 rpdla_status rpdla_kernel_occupancy(int32_t kernel, int32_t field, int32_t precision,
                                     int32_t* vgprs, int32_t* scratch_bytes,

@@ -120,10 +120,14 @@ def test_sweep64_full_size(env):
                      dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
     t0 = time.time()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(s):
+        e0.record(s)
         counts, tallies = P.run_sweep(wl, B.RPDLA_FP64, stream=s, workspace=ws,
                                       electron_steps=steps)
+        e1.record(s)
     s.synchronize()
+    batched_ms = e0.elapsed_time(e1)
     tal = tallies.cpu().numpy()
     _log(f"sweep64 FP64 full size: {time.time() - t0:.1f} s, {int(steps.sum()):.3e} electron-steps")
     assert np.all(tal[:, 0] + tal[:, 1] + tal[:, 4] + tal[:, 5] == n * K)
@@ -132,12 +136,24 @@ def test_sweep64_full_size(env):
                   == tal[:, 0] + tal[:, 1])
     arr = B.batched_chunk_arrays(ws, n_cfg, n, wl["k_first"], wl["k_last"])
     base = wl["cfg_id"] * 1000
-    for c in (0, 27, 63):
+    # every configuration through the single-configuration path too: element by
+    # element against the batched sweep, and the same work timed both ways
+    single_ms = 0.0
+    for c in range(n_cfg):
         rec = wl["lasers"][c]
         L = P.laser_of(rec, wl["field_order"])
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         single = _single(B, L, wl["seed"], base + c, n, wl["k_first"], wl["k_last"],
                          wl["r_factor"], B.RPDLA_FP64, spec)
+        b.record()
+        b.synchronize()
+        single_ms += a.elapsed_time(b)
         _batched_vs_single(torch, B, c, arr, tal, counts, single, n, K, "sweep64")
+        del single
+    _log(f"sweep64 FP64, the same work: batched sweep {batched_ms / 1e3:.2f} s, the 64 "
+         f"configurations one by one through the single-configuration path {single_ms / 1e3:.2f} s "
+         f"(batched / single = {batched_ms / single_ms:.3f})")
     # every configuration: 64 sampled atoms against the oracle, element by
     # element, under the FP64 rule (pooled over the configurations)
     from golden.make_extended_refs import load
