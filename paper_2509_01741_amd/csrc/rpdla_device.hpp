@@ -40,7 +40,7 @@ struct DevCfg {
     // tunnelling rate per normalized time for state k (index k-1):
     //   ln w = c0 - c1h ln|a|^2 - c2 / |a|,   w = 0 where ln w < lnw_zero
     double adk_c0[kMaxStates], adk_c1h[kMaxStates], adk_c2[kMaxStates];
-    double adk_a2thr[kMaxStates];  // |a|^2 below which ln w < lnw_zero - 5 (exact skip)
+    double adk_a2thr[kMaxStates];  // |a|^2 below which ln w < -80 (panels skipped there)
     double lnw_zero;
     double gl_x[4], gl_w[4];       // Gauss-Legendre 4-point nodes / weights on [-1, 1]
     double rr_kappa;               // (2/3) k r_e: Landau-Lifshitz gamma^2 term, normalized

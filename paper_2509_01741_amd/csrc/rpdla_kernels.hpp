@@ -213,7 +213,8 @@ __device__ double solve_crossing(const CFG& c, const AdkState& st, const AtomGeo
     return t;
 }
 
-// Panel range [j_lo, j_hi] outside which the state has w = 0 at every node.
+// Panel range [j_lo, j_hi] outside which the state's ln w lies below the skip
+// level (adk_a2thr) at every node.
 template <class CFG>
 __device__ inline bool state_window(const CFG& c, const AdkState& st, double bound2, double Zc,
                                     double tau_s, double h, int64_t M, int64_t& j_lo, int64_t& j_hi)
@@ -287,6 +288,13 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
                 break;
             }
             j_hi = (target > 0.0) ? nhi : M - 1;
+            if (target > 0.0 && nlo > j) {
+                // before its window the new state's ln w stays below the
+                // skip level at every node, the same bound that starts the
+                // first state at its window: resume at the window's first panel
+                j = nlo - 1;
+                break;
+            }
         }
         if (done) break;
     }

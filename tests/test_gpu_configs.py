@@ -49,7 +49,7 @@ def _oracle_laser(O, rec):
     return O.laser_power(rec["lam"], rec["w0"], rec["tau"], rec["P"])
 
 
-def _batched_vs_single(torch, B, c, arr, tal_b, counts_b, single, n, K, label):
+def _batched_vs_single(torch, B, c, arr, tal_b, counts_b, single, n, K, label, exact=False):
     """Element by element: positions and birth times bit-identical (the same
     sampling and ionization arithmetic), final energies within 1e-8 of the
     single-configuration push for >= 99.9% of the electrons and the same
@@ -75,6 +75,11 @@ def _batched_vs_single(torch, B, c, arr, tal_b, counts_b, single, n, K, label):
          f"changes, histogram L1 {l1}")
     assert (~ok).sum() <= allowed_failures(nb)
     assert (~same).sum() <= allowed_failures(nb)
+    if exact:
+        # the FP64 batched and single pushes compile to the same arithmetic
+        for k, o in zip(("ux", "uy", "uz"), out[:3]):
+            assert torch.equal(arr[k][c, :n].reshape(-1)[fin], o[fin]), (label, c, k)
+        assert l1 == 0
 
 
 def _oracle_check_batched(O, OL, torch, B, arr, c, atoms, seed, cfg_id, r_factor, kf, kl, first,
@@ -149,7 +154,7 @@ def test_sweep64_full_size(env):
         b.record()
         b.synchronize()
         single_ms += a.elapsed_time(b)
-        _batched_vs_single(torch, B, c, arr, tal, counts, single, n, K, "sweep64")
+        _batched_vs_single(torch, B, c, arr, tal, counts, single, n, K, "sweep64", exact=True)
         del single
     _log(f"sweep64 FP64, the same work: batched sweep {batched_ms / 1e3:.2f} s, the 64 "
          f"configurations one by one through the single-configuration path {single_ms / 1e3:.2f} s "
