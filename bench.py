@@ -286,6 +286,51 @@ def measure_sweep(wl, precision, atoms_per_cfg, atoms_per_chunk, chunks_total=No
                 occupancy=occupancy(2, int(wl["field_order"]), precision))
 
 
+def measure_stream(wl, precision):
+    """The whole chunked stream of a batched workload (every chunk of every
+    configuration), run chunk by chunk with rpdla_run_batched_range on one
+    side stream so that each chunk reports as it ends; the chunks are the
+    ones one rpdla_run_batched call would run."""
+    import torch
+    from paper_2509_01741_amd import binding as B
+    from paper_2509_01741_amd import pipeline
+    n_cfg = len(wl["lasers"])
+    spec = pipeline.hist_spec(wl["hist"])
+    dev = torch.device("cuda")
+    n, apc = int(wl["atoms"]), int(wl["chunk"])
+    n_chunks = -(-n // apc)
+    lasers = [pipeline.laser_of(r, wl.get("field_order", 5)) for r in wl["lasers"]]
+    counts = torch.zeros((n_cfg, 2, spec.nE, spec.nA), dtype=torch.int64, device=dev)
+    tallies = torch.zeros((n_cfg, B.RPDLA_NTALLY), dtype=torch.int64, device=dev)
+    steps = torch.zeros(n_cfg, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.rpdla_batched_workspace_bytes(n_cfg, apc, wl["k_first"], wl["k_last"]),
+                     dtype=torch.uint8, device=dev)
+    st = torch.cuda.Stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    total_ms = 0.0
+    for i in range(n_chunks):
+        a, b = ev(), ev()
+        with torch.cuda.stream(st):
+            a.record(st)
+            B.rpdla_run_batched(lasers, wl["seed"], wl["cfg_id"] * 1000, n, apc, wl["r_factor"],
+                                wl["k_first"], wl["k_last"], precision, spec, counts, tallies, ws,
+                                stream=st, electron_steps=steps, chunks=(i, 1))
+            b.record(st)
+        b.synchronize()
+        total_ms += a.elapsed_time(b)
+        log(f"stream {wl['name']}: chunk {i + 1}/{n_chunks} {a.elapsed_time(b) / 1e3:.1f} s")
+    n_steps = int(steps.sum().item())
+    tal = tallies.sum(0).cpu().tolist()
+    bwd = tallies[:, 1].double() / (tallies[:, 0] + tallies[:, 1]).clamp(min=1).double()
+    return dict(workload=wl["name"], precision="mixed" if precision == B.RPDLA_MIXED else "f64",
+                configs=n_cfg, atoms_per_cfg=n, atoms_per_chunk=apc, chunks=n_chunks,
+                ms=round(total_ms, 2), electron_steps=n_steps,
+                electron_steps_per_s=n_steps / (total_ms * 1e-3), born=int(tal[0] + tal[1]),
+                unborn=int(tal[4]), nan=int(tal[5]),
+                backward_fraction_per_config=[round(float(v), 6) for v in bwd.cpu().tolist()])
+
+
 PUSH_KERNEL_NAME = "push_kernel<5, rpdla::ElecF64>"
 TRAFFIC_CMD = ("rocprofv3 --pmc {ctr} --output-format csv -d $R/gpurun_out/{d} -o run -- python3 "
                "$R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-mixed --no-adaptive "
@@ -571,7 +616,7 @@ def ionize_roofline(atoms, ion_ms):
     """Roofline object of the ionization kernel: its FP64 FLOPs per atom come
     from the counter run (the work is data-dependent: panels are skipped where
     the rate bound vanishes, and the Newton iterations vary), taken on the
-    same ensemble at 1e5 atoms, times this launch's atoms over its time."""
+    same ensemble at the same size, times this launch's atoms over its time."""
     crec = _counter_record()
     if crec is None or "ionize" not in crec:
         return None
@@ -580,7 +625,7 @@ def ionize_roofline(atoms, ion_ms):
     return {"bound": "alu", "kernel": "ionize_kernel<5>", "achieved": ach,
             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": None, "flop_per_atom": r["fp64_flop_per_unit"],
-            "flop_source": "executed FP64 FLOPs per atom, counter run at 1e5 atoms of this ensemble",
+            "flop_source": "executed FP64 FLOPs per atom, counter run on this ensemble",
             "valu_per_cu_cycle": r.get("valu_per_cu_cycle"),
             "active_lanes_per_valu_cycle": r.get("active_lanes_per_valu_cycle")}
 
@@ -612,6 +657,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--large-stream", action="store_true",
+                    help="only run the large mixed workload's whole chunked stream and print it")
     ap.add_argument("--no-mixed-workload", action="store_true",
                     help="skip the mixed form's own workload (counter runs read the last launches)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -631,6 +678,10 @@ def main():
     from paper_2509_01741_amd import pipeline, workloads
 
     torch.cuda.set_device(0)
+    if args.large_stream:
+        r = measure_stream(workloads.LARGE_MIXED, B.RPDLA_MIXED)
+        print(json.dumps({"large_stream": r}), flush=True)
+        return
     if args.copy_ref_mib > 0:
         src = torch.ones(args.copy_ref_mib << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -389,6 +389,22 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
                                uint64_t* counts, uint64_t* tallies, uint64_t* electron_steps,
                                void* workspace, size_t ws_bytes, void* stream);
 
+/* The chunks first_chunk .. first_chunk + n_chunks - 1 of the same stream
+ * (n_chunks = -1: to its end), so that a long sweep can be run, timed or
+ * checked in parts: chunk c covers atoms c * atoms_per_chunk onwards of every
+ * configuration, exactly as in rpdla_run_batched, and counts, tallies and
+ * electron_steps accumulate, so consecutive ranges add up to one whole call.
+ * Arguments otherwise as rpdla_run_batched; EINVAL when the range leaves the
+ * stream's cdiv(atoms_per_cfg, atoms_per_chunk) chunks. */
+rpdla_status rpdla_run_batched_range(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t seed,
+                                     uint32_t cfg_base, int64_t atoms_per_cfg,
+                                     int64_t atoms_per_chunk, int64_t first_chunk,
+                                     int64_t n_chunks, double r_factor, int32_t k_first,
+                                     int32_t k_last, int32_t precision,
+                                     const rpdla_hist_spec* spec, uint64_t* counts,
+                                     uint64_t* tallies, uint64_t* electron_steps,
+                                     void* workspace, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Launch-shape autotuning.  Kernel kinds: 0 push, 1 ionize, 2 batched push.
  * A launch shape is the number of threads per block (64, 128, 192, 256) and,

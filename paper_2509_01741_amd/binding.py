@@ -76,6 +76,9 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is not built: run `python -m paper_2509_01741_amd.build` "
             "(hipcc, gfx950); the library has no CPU fallback")
+    # torch is imported above, so the library's HIP calls bind to the HIP
+    # runtime torch already loaded (one runtime per process, one view of the
+    # device); a process that loads librpdla.so before torch gets two
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
     LP = C.POINTER(rpdla_laser)
@@ -103,6 +106,8 @@ def _load():
         "rpdla_batched_graphs": (i32, []),
         "rpdla_run_batched": (i32, [LP, i32, u64, u32, i64, i64, d, i32, i32, i32, HP, vp, vp,
                                     vp, vp, C.c_size_t, vp]),
+        "rpdla_run_batched_range": (i32, [LP, i32, u64, u32, i64, i64, i64, i64, d, i32, i32, i32,
+                                          HP, vp, vp, vp, vp, C.c_size_t, vp]),
         "rpdla_autotune": (i32, [LP, i32, i64, i32, i32, C.c_char_p, C.c_size_t, vp]),
         "rpdla_set_launch_shape": (i32, [i32, i32, i32, i32, i32]),
         "rpdla_get_launch_shape": (i32, [i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -412,9 +417,12 @@ def batched_chunk_arrays(workspace, n_cfg, atoms_per_chunk, k_first, k_last) -> 
 
 def rpdla_run_batched(lasers, seed, cfg_base, atoms_per_cfg, atoms_per_chunk, r_factor, k_first,
                       k_last, precision, spec: rpdla_hist_spec, counts=None, tallies=None,
-                      workspace=None, stream=None, device=None, electron_steps=None):
+                      workspace=None, stream=None, device=None, electron_steps=None,
+                      chunks=None):
     """Returns (counts [n_cfg, 2, nE, nA], tallies [n_cfg, 6]); electron_steps,
-    if given, is an int64 tensor [n_cfg] that accumulates the RK4 steps."""
+    if given, is an int64 tensor [n_cfg] that accumulates the RK4 steps.
+    chunks=(first, count) runs only those chunks of the stream
+    (rpdla_run_batched_range)."""
     n_cfg = len(lasers)
     arr = (rpdla_laser * n_cfg)(*lasers)
     nb = 2 * spec.nE * spec.nA
@@ -426,13 +434,16 @@ def rpdla_run_batched(lasers, seed, cfg_base, atoms_per_cfg, atoms_per_chunk, r_
     need = rpdla_batched_workspace_bytes(n_cfg, atoms_per_chunk, k_first, k_last)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=counts.device)
-    _check(lib.rpdla_run_batched(arr, n_cfg, seed, cfg_base, atoms_per_cfg, atoms_per_chunk,
-                                 r_factor, k_first, k_last, precision, C.byref(spec),
-                                 _dev(counts, "counts", n_cfg * nb, torch.int64),
-                                 _dev(tallies, "tallies", n_cfg * RPDLA_NTALLY, torch.int64),
-                                 (C.c_void_p(0) if electron_steps is None else
-                                  _dev(electron_steps, "electron_steps", n_cfg, torch.int64)),
-                                 _dev(workspace, "workspace", need, torch.uint8),
-                                 C.c_size_t(workspace.numel()), _stream(stream)),
-           "rpdla_run_batched")
+    first, count = (0, -1) if chunks is None else chunks
+    _check(lib.rpdla_run_batched_range(arr, n_cfg, seed, cfg_base, atoms_per_cfg, atoms_per_chunk,
+                                       first, count, r_factor, k_first, k_last, precision,
+                                       C.byref(spec),
+                                       _dev(counts, "counts", n_cfg * nb, torch.int64),
+                                       _dev(tallies, "tallies", n_cfg * RPDLA_NTALLY, torch.int64),
+                                       (C.c_void_p(0) if electron_steps is None else
+                                        _dev(electron_steps, "electron_steps", n_cfg,
+                                             torch.int64)),
+                                       _dev(workspace, "workspace", need, torch.uint8),
+                                       C.c_size_t(workspace.numel()), _stream(stream)),
+           "rpdla_run_batched_range" if chunks is not None else "rpdla_run_batched")
     return counts, tallies

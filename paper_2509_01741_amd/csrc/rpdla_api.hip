@@ -836,6 +836,20 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
                                uint64_t* electron_steps, void* workspace, size_t ws_bytes,
                                void* stream)
 {
+    return rpdla_run_batched_range(cfgs, n_cfg, seed, cfg_base, atoms_per_cfg, atoms_per_chunk, 0,
+                                   -1, r_factor, k_first, k_last, precision, spec, counts, tallies,
+                                   electron_steps, workspace, ws_bytes, stream);
+}
+
+rpdla_status rpdla_run_batched_range(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t seed,
+                                     uint32_t cfg_base, int64_t atoms_per_cfg,
+                                     int64_t atoms_per_chunk, int64_t first_chunk,
+                                     int64_t n_chunks_run, double r_factor, int32_t k_first,
+                                     int32_t k_last, int32_t precision,
+                                     const rpdla_hist_spec* spec, uint64_t* counts,
+                                     uint64_t* tallies, uint64_t* electron_steps,
+                                     void* workspace, size_t ws_bytes, void* stream)
+{
     if (!cfgs) return fail(RPDLA_EINVAL, "cfgs is NULL");
     if (n_cfg < 1) return fail(RPDLA_EINVAL, "n_cfg must be >= 1");
     if (n_cfg > 64) return fail(RPDLA_EUNSUPPORTED, "at most 64 configurations per call");
@@ -862,6 +876,12 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
     if ((int64_t)n_cfg * spec->nE * spec->nA > ((int64_t)1 << 28))
         return fail(RPDLA_ERANGE, "too many histogram bins");
     if (!counts || !tallies || !workspace) return fail(RPDLA_EINVAL, "null pointer");
+    const int64_t n_total = cdiv(atoms_per_cfg, atoms_per_chunk);
+    const int64_t n_chunks = n_chunks_run < 0 ? n_total - first_chunk : n_chunks_run;
+    if (first_chunk < 0 || first_chunk > n_total || n_chunks < 0 || n_chunks > n_total - first_chunk)
+        return fail(RPDLA_EINVAL, "chunks [%lld, %lld) outside the stream's %lld chunks",
+                    (long long)first_chunk, (long long)(first_chunk + n_chunks),
+                    (long long)n_total);
     if (((uintptr_t)workspace & 255) != 0) return fail(RPDLA_EINVAL, "workspace must be 256-byte aligned");
     const int K = k_last - k_first + 1;
     if ((double)n_cfg * (double)atoms_per_chunk * K > 1.0e12)
@@ -901,9 +921,9 @@ rpdla_status rpdla_run_batched(const rpdla_laser* cfgs, int32_t n_cfg, uint64_t 
         hipLaunchKernelGGL(rpdla::batch_set_cfg_kernel, dim3(1), dim3(64), 0, s, dc, rmax, zh,
                            (DevCfg*)(base + w.cfg), (double*)(base + w.geo), c);
     }
-    hipLaunchKernelGGL(rpdla::batch_reset_kernel, dim3(1), dim3(64), 0, s, A.ctl);
+    hipLaunchKernelGGL(rpdla::batch_reset_kernel, dim3(1), dim3(64), 0, s, A.ctl,
+                       (unsigned long long)first_chunk);
     RPDLA_HIP(hipGetLastError());
-    const int64_t n_chunks = cdiv(atoms_per_cfg, atoms_per_chunk);
     if (n_chunks == 0) return RPDLA_OK;
     const bool mixed = precision == RPDLA_MIXED;
     switch (cfgs[0].field) {

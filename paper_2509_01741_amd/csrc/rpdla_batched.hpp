@@ -46,10 +46,10 @@ __global__ void batch_set_cfg_kernel(DevCfg c, double r_max, double z_half, DevC
     }
 }
 
-__global__ void batch_reset_kernel(BatchCtl* ctl)
+__global__ void batch_reset_kernel(BatchCtl* ctl, unsigned long long first_chunk)
 {
     if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) ctl->chunk = 0ull;
+        if (threadIdx.x == 0) ctl->chunk = first_chunk;
         if (threadIdx.x < kMaxCfg) ctl->queue[threadIdx.x] = 0ull;
     }
 }

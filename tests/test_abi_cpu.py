@@ -22,10 +22,14 @@ def _declared():
 
 @pytest.fixture(scope="module")
 def lib():
+    # loaded through the binding, which imports torch first: a library loaded
+    # before torch binds to a second HIP runtime, and the GPU tests that may
+    # follow in the same process would then see two
     if not os.path.exists(LIB):
         from paper_2509_01741_amd.build import build_library
         build_library(force=False)
-    return C.CDLL(LIB)
+    from paper_2509_01741_amd import binding as B
+    return B.lib
 
 
 def test_header_symbols_exported(lib):
@@ -105,6 +109,11 @@ def test_validation_without_gpu():
                                  0, p) == B.RPDLA_EUNSUPPORTED
     assert lib.rpdla_run_batched(arr, 2, 0, 0, 10, 10, 2.0, 1, 10, 0, C.byref(sp), C.c_void_p(256),
                                  C.c_void_p(512), p, C.c_void_p(1024), 16, p) == B.RPDLA_ENOMEM
+    # chunk ranges outside a 2-chunk stream (20 atoms, 10 per chunk), checked before any launch
+    for first, cnt in ((-1, 1), (0, 3), (3, -1), (1, 2)):
+        assert lib.rpdla_run_batched_range(arr, 2, 0, 0, 20, 10, first, cnt, 2.0, 1, 10, 0,
+                                           C.byref(sp), C.c_void_p(256), C.c_void_p(512), p,
+                                           C.c_void_p(1024), 1 << 40, p) == B.RPDLA_EINVAL
     arr[1].field = 1
     assert lib.rpdla_run_batched(arr, 2, 0, 0, 10, 10, 2.0, 1, 10, 0, C.byref(sp), p, p, p, p, 0,
                                  p) == B.RPDLA_EINVAL

@@ -2,6 +2,8 @@
 LDS configuration table, per-configuration queues, separate binning pass,
 hipGraph chunk replay) against the
 single-configuration path and the oracle."""
+import sys
+
 import numpy as np
 import pytest
 
@@ -134,3 +136,40 @@ def test_single_chunk_graph_replays(env):
         assert float(torch.arange(1000, device="cuda", dtype=torch.float64).sum()) == 499500.0
         assert torch.equal(counts, c0) and torch.equal(tallies, t0), rep
         assert B.rpdla_batched_graphs() == g0 + 1
+
+
+def test_chunk_ranges_add_up_to_the_whole_stream(env):
+    """rpdla_run_batched_range: a 3-chunk stream run as chunk 0, then chunks
+    1..2 (graph-replayed on a side stream), gives the counts, tallies and
+    electron-steps of one whole call, and leaves the last chunk's arrays of the
+    whole call."""
+    torch, B, O = env
+    lasers = _lasers(B)
+    spec = B.rpdla_hist_spec(*SPEC)
+    n, apc, K = 70, 25, 10                       # chunks of 25, 25 and 20 atoms
+    ws_a = torch.empty(B.rpdla_batched_workspace_bytes(3, apc, 1, K), dtype=torch.uint8,
+                       device="cuda")
+    ws_b = torch.empty_like(ws_a)
+    st_a = torch.zeros(3, dtype=torch.int64, device="cuda")
+    st_b = torch.zeros(3, dtype=torch.int64, device="cuda")
+    c_a, t_a = B.rpdla_run_batched(lasers, 6, 11, n, apc, 2.0, 1, K, 0, spec, workspace=ws_a,
+                                   electron_steps=st_a)
+    c_b, t_b = B.rpdla_run_batched(lasers, 6, 11, n, apc, 2.0, 1, K, 0, spec, workspace=ws_b,
+                                   electron_steps=st_b, chunks=(0, 1))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        B.rpdla_run_batched(lasers, 6, 11, n, apc, 2.0, 1, K, 0, spec, c_b, t_b, ws_b, stream=s,
+                            electron_steps=st_b, chunks=(1, -1))
+    s.synchronize()
+    print(f"[batched] chunk ranges: {int(st_a.sum())} electron-steps whole, "
+          f"{int(st_b.sum())} in parts", file=sys.stderr, flush=True)
+    assert torch.equal(c_a, c_b) and torch.equal(t_a, t_b) and torch.equal(st_a, st_b)
+    arr_a = B.batched_chunk_arrays(ws_a, 3, apc, 1, K)
+    arr_b = B.batched_chunk_arrays(ws_b, 3, apc, 1, K)
+    assert torch.equal(arr_a["x"][:, :20], arr_b["x"][:, :20])
+    tb = arr_a["t_birth"][:, :20]
+    assert torch.equal(tb, arr_b["t_birth"][:, :20])
+    born = torch.isfinite(tb)                    # momenta are written for born slots only
+    for k in ("ux", "uz"):
+        assert torch.equal(arr_a[k][:, :20][born], arr_b[k][:, :20][born]), k
