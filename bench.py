@@ -28,15 +28,16 @@ C_LIGHT = 299792458.0
 # FP64 floating-point operations of one RK4 step of one electron with the
 # order-5 radial field, counted from the implemented formulas (mul, add and
 # the hardware reciprocal / reciprocal-square-root estimates = 1 FLOP,
-# fma = 2; the sine/cosine, exponential, reciprocal and reciprocal square root
+# fma = 2; the carrier, exponential, reciprocal and reciprocal square root
 # at the operations of their polynomial and Newton sequences).  Per
-# right-hand side: field 186 (position terms 8, reciprocal 7, phase and
-# envelope arguments 7, exponential 29, sine/cosine of the two-part phase 40,
-# amplitude 5, w-recurrence 30, brackets 57, radial and axial scales 3) +
-# Lorentz 27 (gamma 15, velocity 3, force from the radial parts 9); per step
-# 4 x 213 + RK4 115 (stage arguments 48, slope sums 24, increments 15,
-# compensated sums of the seven state variables 28) = 967.
-ALGO_FLOP_PER_STEP = 967.0
+# right-hand side: field 183 (position terms 8, reciprocal 7, phase and
+# envelope arguments 7, exponential 29, half-angle carrier of the two-part
+# phase 39, amplitude with cos = 1 - sigma^2 and sin = sigma kappa 7,
+# w-recurrence 30, brackets 54, axial and radial scales 2) + Lorentz 27
+# (gamma 15, velocity 3, force from the radial parts 9); per step 4 x 210 +
+# RK4 115 (stage arguments 48, slope sums 24, increments 15, compensated sums
+# of the seven state variables 28) = 955.
+ALGO_FLOP_PER_STEP = 955.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # Published FP32 vector peak (it counts packed FP32 FMAs; the kernels are
 # compiled without packed FP32).

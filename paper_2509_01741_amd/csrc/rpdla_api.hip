@@ -150,6 +150,7 @@ DevCfg make_cfg(const rpdla_laser* L)
     c.ta_n = om * L->t_after;
     c.er_scale = L->er_scale; c.ez_scale = L->ez_scale;
     c.er_w = c.er_scale * c.inv_w0n; c.ez_e = c.ez_scale * c.eps;
+    c.a0_w = c.a0 * c.inv_w0n; c.ez_2 = 2.0 * c.ez_scale;
     for (int i = 0; i < 3; ++i) {
         c.tE[i] = kQe * L->test_E[i] / (kMe * kC * om);
         c.tB[i] = kQe * L->test_B[i] / (kMe * om);

@@ -117,8 +117,13 @@ __global__ void __launch_bounds__(256, 2) batch_ionize_kernel(BatchArgs A)
 // spilling them.  The step's vector registers hold electron state only.  Final
 // momenta go to the chunk's u arrays (NaN for invalid births; unborn and
 // inactive slots are not written).
+// Register budgets: as the single push, except that the mixed form keeps 6
+// waves (its queue switching needs a few more registers than 7 waves leave).
+template <class E> struct BatchWaves { static constexpr int value = ElecWaves<E>::value; };
+template <> struct BatchWaves<ElecMixed> { static constexpr int value = 6; };
+
 template <int FIELD, class ELEC>
-__global__ void __launch_bounds__(256, ElecWaves<ELEC>::value) batch_push_kernel(
+__global__ void __launch_bounds__(256, BatchWaves<ELEC>::value) batch_push_kernel(
     BatchArgs A, const DevCfg* __restrict__ cfgs)
 {
     extern __shared__ unsigned long long s_steps[];   // [n_cfg] steps taken in this block

@@ -35,6 +35,8 @@ struct DevCfg {
     double tb_n, ta_n;           // omega t_before, omega t_after
     double er_scale, ez_scale;
     double er_w, ez_e;           // er_scale/(k w0) and ez_scale eps (folded products)
+    double a0_w, ez_2;           // a0/(k w0) and 2 ez_scale: the FP64 radial field
+                                 // carries 1/(k w0) in its amplitude (ez_scale eps k w0 = 2 ez_scale)
     double tE[3], tB[3];         // normalized uniform test fields
     int32_t field, window;
     // tunnelling rate per normalized time for state k (index k-1):
@@ -141,10 +143,15 @@ __device__ inline void rp_brackets(T G_re, T G_im, T zeta, T rD, T E, T& PE, T& 
     PB = Rr[2];
     EZe = fma(-rD, Ri[3], Ri[2]);
     if constexpr (ORDER >= 3) {
-        const T h3 = T(0.5) * Rr[3], q5 = T(0.25) * Rr[5];
-        const T pe2 = fma(fma(-q5, rD, Rr[4]), rD, -h3);
-        const T pb2 = fma(fma(-q5, rD, T(0.5) * Rr[4]), rD, h3);
-        const T ez3 = fma(fma(fma(T(0.25) * Ri[6], rD, T(-1.25) * Ri[5]), rD, T(0.5) * Ri[4]), rD,
+        // first-order brackets in v = rD/2 (fewer constant factors):
+        //   pe2 = 2 R4 v - R5 v^2 - R3/2,  pb2 = R4 v - R5 v^2 + R3/2,
+        //   ez3 = 2 I6 v^3 - 5 I5 v^2 + I4 v + I3/2
+        const T v = T(0.5) * rD;
+        const T h3 = T(0.5) * Rr[3];
+        const T a = fma(-Rr[5], v, Rr[4]);
+        const T pb2 = fma(a, v, h3);
+        const T pe2 = fma(a + Rr[4], v, -h3);
+        const T ez3 = fma(fma(fma(Ri[6] + Ri[6], v, T(-5.0) * Ri[5]), v, Ri[4]), v,
                           T(0.5) * Ri[3]);
         EZe = fma(E, ez3, EZe);
         if constexpr (ORDER >= 5) {
@@ -178,15 +185,18 @@ __device__ inline void rp_field_parts_f64(const CFG& c, double X, double Y, doub
     const double rD = r2 * iD;
     const double psi_lo = fma(-rD, zeta, LO ? c.phi0 + dl : c.phi0);
     const double s = (LO ? d + dl : d) * c.inv_T0n;
-    const double g = c.a0 * fm::exp_fin_f64(-rD - s * s);
-    double sn, cs;
-    fm::sincos2_f64(d, psi_lo, &sn, &cs);
-    const double gi = g * (iD * iD);
+    const double g = c.a0_w * fm::exp_fin_f64(-rD - s * s);
+    // g e^{i Psi} / D from the half-angle form: the sign (-1)^n goes on the
+    // amplitude, cos Psi = 1 - sigma^2 and sin Psi = sigma kappa
+    double sg, kp;
+    const unsigned sgn = fm::cis_half2_f64(d, psi_lo, &sg, &kp);
+    const double gi = fm::flip_sign(g * (iD * iD), sgn);
+    const double gs = gi * sg;
     double PE, PB, EZe;
-    rp_brackets<ORDER, double>(gi * cs, gi * sn, zeta, rD, c.e2 * iD, PE, PB, EZe);
-    pe = c.er_w * PE;
-    pb = PB * c.inv_w0n;
-    az = c.ez_e * EZe;
+    rp_brackets<ORDER, double>(fma(-gs, sg, gi), gs * kp, zeta, rD, c.e2 * iD, PE, PB, EZe);
+    pe = c.er_scale * PE;
+    pb = PB;
+    az = c.ez_2 * EZe;
 }
 
 // The radial field in Cartesian components.  WANT_B = false skips the

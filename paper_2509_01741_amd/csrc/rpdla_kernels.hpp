@@ -156,8 +156,10 @@ __device__ inline double emag2_atom(const CFG& c, const AtomGeom& a, double d)
     if constexpr (FIELD == 1 || FIELD == 3 || FIELD == 5) {
         const double s = d * c.inv_T0n;
         const double g = c.a0 * fm::exp_f64(a.mrD - s * s);
-        double sn, cs;
-        fm::sincos2_f64(d, a.psi_c, &sn, &cs);
+        // the sign (-1)^n of the half-angle form cancels in the squares
+        double sg, kp;
+        fm::cis_half2_f64(d, a.psi_c, &sg, &kp);
+        const double cs = fma(-sg, sg, 1.0), sn = sg * kp;
         const double et = c.er_scale * g * (cs * a.aer - sn * a.aei);
         const double ez = c.ez_scale * g * (sn * a.azr + cs * a.azi);
         return et * et * a.r2 + ez * ez;
@@ -932,7 +934,7 @@ __device__ inline int64_t queue_take(unsigned long long* queue, bool need)
 // at 7 without spills, 1-5% faster than 5), controlled-step unbounded (six
 // stored stages, 2 waves).
 template <class E> struct ElecWaves { static constexpr int value = 4; };
-template <> struct ElecWaves<ElecMixed> { static constexpr int value = 6; };
+template <> struct ElecWaves<ElecMixed> { static constexpr int value = 7; };
 template <> struct ElecWaves<ElecDP> { static constexpr int value = 1; };
 
 template <int FIELD, class ELEC>

@@ -21,6 +21,14 @@ extern "C" void fm_sincos(long n, const double* x, double* s, double* c) {
 extern "C" void fm_sincos2(long n, const double* xh, const double* xl, double* s, double* c) {
     for (long i = 0; i < n; ++i) rpdla::fm::sincos2_f64(xh[i], xl[i], s + i, c + i);
 }
+extern "C" void fm_cis_half2(long n, const double* xh, const double* xl, double* s, double* c) {
+    for (long i = 0; i < n; ++i) {
+        double sg, kp;
+        const unsigned m = rpdla::fm::cis_half2_f64(xh[i], xl[i], &sg, &kp);
+        s[i] = rpdla::fm::flip_sign(sg * kp, m);
+        c[i] = rpdla::fm::flip_sign(1.0 - sg * sg, m);
+    }
+}
 extern "C" void fm_exp(long n, const double* x, double* y) {
     for (long i = 0; i < n; ++i) y[i] = rpdla::fm::exp_f64(x[i]);
 }
@@ -50,6 +58,7 @@ def fm(tmp_path_factory):
     lib.fm_exp.argtypes = [C.c_long, P, P]
     lib.fm_sincos2.argtypes = [C.c_long, P, P, P, P]
     lib.fm_exp_fin.argtypes = [C.c_long, P, P]
+    lib.fm_cis_half2.argtypes = [C.c_long, P, P, P, P]
     lib.fm_rcp.argtypes = [C.c_long, P, P]
     lib.fm_rsqrt.argtypes = [C.c_long, P, P]
     return lib
@@ -101,6 +110,33 @@ def test_sincos_of_unevaluated_sum(fm):
     s1 = np.zeros_like(xh); c1 = np.zeros_like(xh)
     fm.fm_sincos(xh.size, xh + xl, s1, c1)
     assert np.abs(s1 - ref_s).max() / 2.0**-53 > 4 * es.max()
+
+
+def test_half_angle_cis_of_unevaluated_sum(fm):
+    """The half-angle form of e^{ix} (x = n pi + r, sigma = sqrt2 sin(r/2),
+    kappa = sqrt2 cos(r/2), cos x = (-1)^n (1 - sigma^2), sin x = (-1)^n
+    sigma kappa) against mpmath for phases up to 1e3 with a low part of a few
+    units, the multiples of pi/2 and pi/4 (where the reduction switches n or
+    the identities cancel most), and tiny arguments."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.prec = 120
+    rng = np.random.default_rng(8)
+    k = np.arange(-4000, 4001)
+    xh = np.concatenate([rng.uniform(-1e3, 1e3, 3000), k * np.pi / 2, k * np.pi / 4,
+                         rng.uniform(-1e-3, 1e-3, 200), [0.0, 1e-300, -1e-300]])
+    xl = np.concatenate([rng.uniform(-4, 4, 3000), np.zeros(xh.size - 3000)])
+    s = np.zeros_like(xh); c = np.zeros_like(xh)
+    fm.fm_cis_half2(xh.size, xh, xl, s, c)
+    ref_s = np.array([float(mp.sin(mp.mpf(a) + mp.mpf(b))) for a, b in zip(xh, xl)])
+    ref_c = np.array([float(mp.cos(mp.mpf(a) + mp.mpf(b))) for a, b in zip(xh, xl)])
+    es = np.abs(s - ref_s) / 2.0**-53
+    ec = np.abs(c - ref_c) / 2.0**-53
+    # absolute errors: a few units of 2^-53 (1 - sigma^2 cancels near cos x = 0)
+    assert es.max() <= 8 and ec.max() <= 8, (es.max(), ec.max())
+    # sine relative to its size near zero: sigma kappa keeps it
+    small = np.abs(ref_s) < 1e-3
+    rel = np.abs(s[small] - ref_s[small]) / np.maximum(np.abs(ref_s[small]), 1e-300)
+    assert rel.max() <= 8 * 2.0**-53, rel.max()
 
 
 def test_exp_against_libm(fm):

@@ -281,7 +281,7 @@ def test_kernel_occupancy(env):
     """The push and ionize kernels keep every value in registers (no scratch)
     and reach the resident waves their launch bounds ask for."""
     torch, B, O = env
-    want = {(B.RPDLA_KERNEL_PUSH, B.RPDLA_FP64): 4, (B.RPDLA_KERNEL_PUSH, B.RPDLA_MIXED): 6,
+    want = {(B.RPDLA_KERNEL_PUSH, B.RPDLA_FP64): 4, (B.RPDLA_KERNEL_PUSH, B.RPDLA_MIXED): 7,
             (B.RPDLA_KERNEL_IONIZE, B.RPDLA_FP64): 3, (B.RPDLA_KERNEL_BATCHED_PUSH, B.RPDLA_FP64): 4,
             (B.RPDLA_KERNEL_BATCHED_PUSH, B.RPDLA_MIXED): 6}
     for (kind, prec), waves in want.items():
