@@ -704,26 +704,74 @@ __device__ inline void elec_final(const CFG& c, const ElecDP& e, double& ux, dou
 
 // ---------------------------------------------------------------------------
 // Mixed precision: the field and the RK4 stage arithmetic in float; time,
-// position and the carrier phase in double.  The phase tau - Z is formed in
-// double and reduced to turns in [-1/2, 1/2] before the float sine/cosine
-// (the hardware sine/cosine take turns); the momentum is kept in float with
-// a Kahan compensation term.
+// position and the carrier phase in double.  At each step start the retarded
+// time tau - Z is formed in double and reduced to turns in [-1/2, 1/2] (the
+// hardware sine/cosine take turns); the four stages then take the transverse
+// position, zeta, the phase and the envelope argument as float offsets from
+// that start -- the field needs them only to float precision, and the
+// retarded time advances by h (1 - beta_z) over a stage of length h.  The
+// momentum is kept in float with a Kahan compensation term, the position in
+// double.
 // ---------------------------------------------------------------------------
-template <int ORDER, class CFG>
-__device__ inline void rp_field_parts_mixed(const CFG& c, double X, double Y, double Z, double tau,
-                                            float& pe, float& pb, float& az)
+
+// Field arguments at the step start, in float (phase and envelope from the
+// double retarded time).
+struct MixedBase {
+    float X, Y;        // transverse position
+    float zeta;        // Z / (k z_r)
+    float ph;          // (tau - Z) / (2 pi), reduced to [-1/2, 1/2]
+    float s;           // (tau - Z) / (omega tau0)
+    float izr, it0;    // 1/(k z_r), 1/(omega tau0)
+};
+
+template <class CFG>
+__device__ inline MixedBase mixed_base(const CFG& c, double tau, double X, double Y, double Z)
 {
     const double d = tau - Z;
     double turns = d * kInvTwoPi;
     turns -= rint(turns);
-    const float Xf = (float)X, Yf = (float)Y;
-    const float r2 = (Xf * Xf + Yf * Yf) * (float)c.inv_w0n2;
-    const float zeta = (float)(Z * c.inv_zrn);
+    MixedBase b;
+    b.X = (float)X; b.Y = (float)Y;
+    b.zeta = (float)(Z * c.inv_zrn);
+    b.ph = (float)turns;
+    b.s = (float)(d * c.inv_T0n);
+    b.izr = (float)c.inv_zrn;
+    b.it0 = (float)c.inv_T0n;
+    return b;
+}
+
+// Field arguments of a stage at offset hk from the step start, reached with
+// the slopes (kX, kY, kZ); dd is the retarded-time offset hk (1 - kZ).
+struct MixedArgs {
+    float X, Y, zeta, dd, s;
+};
+
+template <bool FIRST>
+__device__ inline MixedArgs mixed_args(const MixedBase& b, float hk, float kX, float kY, float kZ)
+{
+    MixedArgs a;
+    if constexpr (FIRST) {
+        a.X = b.X; a.Y = b.Y; a.zeta = b.zeta; a.dd = 0.f; a.s = b.s;
+    } else {
+        a.X = fmaf(hk, kX, b.X);
+        a.Y = fmaf(hk, kY, b.Y);
+        a.zeta = fmaf(hk * kZ, b.izr, b.zeta);
+        a.dd = fmaf(-hk, kZ, hk);
+        a.s = fmaf(a.dd, b.it0, b.s);
+    }
+    return a;
+}
+
+template <int ORDER, class CFG>
+__device__ inline void rp_field_parts_mixed(const CFG& c, const MixedBase& b, const MixedArgs& a,
+                                            float& pe, float& pb, float& az)
+{
+    const float r2 = (a.X * a.X + a.Y * a.Y) * (float)c.inv_w0n2;
+    const float zeta = a.zeta;
     const float iD = __builtin_amdgcn_rcpf(1.0f + zeta * zeta);
     const float rD = r2 * iD;
-    const float ph = (float)turns + ((float)c.phi0 - rD * zeta) * (float)kInvTwoPi;
-    const float s = (float)(d * c.inv_T0n);
-    const float g = (float)c.a0 * __builtin_amdgcn_exp2f(-(rD + s * s) * 1.4426950408889634f);
+    const float ph = fmaf(a.dd + fmaf(-rD, zeta, (float)c.phi0), (float)kInvTwoPi, b.ph);
+    const float g = (float)c.a0 * __builtin_amdgcn_exp2f(-(rD + a.s * a.s) * 1.4426950408889634f);
     const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
     const float gi = g * (iD * iD);
     float PE, PB, EZe;
@@ -733,19 +781,8 @@ __device__ inline void rp_field_parts_mixed(const CFG& c, double X, double Y, do
     az = (float)c.ez_e * EZe;
 }
 
-template <int ORDER, class CFG>
-__device__ inline void rp_field_mixed(const CFG& c, double X, double Y, double Z, double tau,
-                                      float& ax, float& ay, float& az, float& bx, float& by)
-{
-    float pe, pb;
-    rp_field_parts_mixed<ORDER>(c, X, Y, Z, tau, pe, pb, az);
-    const float Xf = (float)X, Yf = (float)Y;
-    ax = pe * Xf; ay = pe * Yf;
-    bx = -pb * Yf; by = pb * Xf;
-}
-
 template <int FIELD, class CFG>
-__device__ inline void field_mixed(const CFG& c, double X, double Y, double Z, double tau,
+__device__ inline void field_mixed(const CFG& c, const MixedBase& b, const MixedArgs& a,
                                    float& ax, float& ay, float& az, float& bx, float& by,
                                    float& bz)
 {
@@ -754,38 +791,39 @@ __device__ inline void field_mixed(const CFG& c, double X, double Y, double Z, d
         ax = (float)c.tE[0]; ay = (float)c.tE[1]; az = (float)c.tE[2];
         bx = (float)c.tB[0]; by = (float)c.tB[1]; bz = (float)c.tB[2];
     } else if constexpr (FIELD == 10) {
-        const double d = tau - Z;
-        double turns = (d + c.phi0) * kInvTwoPi;
-        turns -= rint(turns);
-        const float s = (float)(d * c.inv_T0n);
-        const float e = (float)c.a0 * __builtin_amdgcn_exp2f(-s * s * 1.4426950408889634f)
-                        * __builtin_amdgcn_cosf((float)turns);
+        const float ph = fmaf(a.dd + (float)c.phi0, (float)kInvTwoPi, b.ph);
+        const float e = (float)c.a0 * __builtin_amdgcn_exp2f(-a.s * a.s * 1.4426950408889634f)
+                        * __builtin_amdgcn_cosf(ph);
         ax = e; ay = 0.f; az = 0.f; bx = 0.f; by = e; bz = 0.f;
     } else {
-        rp_field_mixed<FIELD, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by);
+        float pe, pb;
+        rp_field_parts_mixed<FIELD>(c, b, a, pe, pb, az);
+        ax = pe * a.X; ay = pe * a.Y;
+        bx = -pb * a.Y; by = pb * a.X;
         bz = 0.f;
     }
 }
 
-template <int FIELD, class CFG>
-__device__ inline void rhs_mixed(const CFG& c, double tau, double X, double Y, double Z, float ux,
-                                 float uy, float uz, float& dX, float& dY, float& dZ, float& dux,
-                                 float& duy, float& duz)
+template <int FIELD, bool FIRST, class CFG>
+__device__ inline void rhs_mixed(const CFG& c, const MixedBase& b, float hk, float& dX, float& dY,
+                                 float& dZ, float ux, float uy, float uz, float& dux, float& duy,
+                                 float& duz)
 {
+    // (dX, dY, dZ) come in as the previous stage's slopes and leave as this one's
+    const MixedArgs a = mixed_args<FIRST>(b, hk, dX, dY, dZ);
     const float ig = __builtin_amdgcn_rsqf(1.0f + ux * ux + uy * uy + uz * uz);
     dX = ux * ig; dY = uy * ig; dZ = uz * ig;
     if constexpr (FIELD == 1 || FIELD == 3 || FIELD == 5) {
         // radial field: the force from its radial and axial parts, as in rhs_f64
         float pe, pb, az;
-        rp_field_parts_mixed<FIELD>(c, X, Y, Z, tau, pe, pb, az);
-        const float Xf = (float)X, Yf = (float)Y;
+        rp_field_parts_mixed<FIELD>(c, b, a, pe, pb, az);
         const float f = fmaf(-dZ, pb, pe);
-        dux = -f * Xf;
-        duy = -f * Yf;
-        duz = -fmaf(pb, fmaf(dY, Yf, dX * Xf), az);
+        dux = -f * a.X;
+        duy = -f * a.Y;
+        duz = -fmaf(pb, fmaf(dY, a.Y, dX * a.X), az);
     } else {
         float ax, ay, az, bx, by, bz;
-        field_mixed<FIELD, CFG>(c, X, Y, Z, tau, ax, ay, az, bx, by, bz);
+        field_mixed<FIELD, CFG>(c, b, a, ax, ay, az, bx, by, bz);
         dux = -(ax + dY * bz - dZ * by);
         duy = -(ay + dZ * bx - dX * bz);
         duz = -(az + dX * by - dY * bx);
@@ -828,20 +866,20 @@ __device__ inline void elec_step(const CFG& c, ElecMixed& e)
     const double ta = e.tau0 + (double)e.n * h;
     const double hsd = (e.n == e.N - 1) ? (e.taue - ta) : h;
     const float hs = (float)hsd, hh = 0.5f * hs;
-    const double hhd = 0.5 * hsd;
+    const MixedBase b = mixed_base(c, ta, e.X, e.Y, e.Z);
     float kX, kY, kZ, kx, ky, kz, aX, aY, aZ, ax, ay, az;
-    rhs_mixed<FIELD>(c, ta, e.X, e.Y, e.Z, e.ux, e.uy, e.uz, kX, kY, kZ, kx, ky, kz);
+    rhs_mixed<FIELD, true>(c, b, 0.f, kX, kY, kZ, e.ux, e.uy, e.uz, kx, ky, kz);
     aX = kX; aY = kY; aZ = kZ; ax = kx; ay = ky; az = kz;
-    rhs_mixed<FIELD>(c, ta + hhd, e.X + hhd * kX, e.Y + hhd * kY, e.Z + hhd * kZ, e.ux + hh * kx,
-                     e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_mixed<FIELD, false>(c, b, hh, kX, kY, kZ, e.ux + hh * kx, e.uy + hh * ky, e.uz + hh * kz,
+                            kx, ky, kz);
     aX += 2.f * kX; aY += 2.f * kY; aZ += 2.f * kZ;
     ax += 2.f * kx; ay += 2.f * ky; az += 2.f * kz;
-    rhs_mixed<FIELD>(c, ta + hhd, e.X + hhd * kX, e.Y + hhd * kY, e.Z + hhd * kZ, e.ux + hh * kx,
-                     e.uy + hh * ky, e.uz + hh * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_mixed<FIELD, false>(c, b, hh, kX, kY, kZ, e.ux + hh * kx, e.uy + hh * ky, e.uz + hh * kz,
+                            kx, ky, kz);
     aX += 2.f * kX; aY += 2.f * kY; aZ += 2.f * kZ;
     ax += 2.f * kx; ay += 2.f * ky; az += 2.f * kz;
-    rhs_mixed<FIELD>(c, ta + hsd, e.X + hsd * kX, e.Y + hsd * kY, e.Z + hsd * kZ, e.ux + hs * kx,
-                     e.uy + hs * ky, e.uz + hs * kz, kX, kY, kZ, kx, ky, kz);
+    rhs_mixed<FIELD, false>(c, b, hs, kX, kY, kZ, e.ux + hs * kx, e.uy + hs * ky, e.uz + hs * kz,
+                            kx, ky, kz);
     const double w6d = hsd * (1.0 / 6.0);
     const float w6 = hs * (1.0f / 6.0f);
     e.X += w6d * (double)(aX + kX); e.Y += w6d * (double)(aY + kY); e.Z += w6d * (double)(aZ + kZ);
