@@ -94,7 +94,7 @@ def electron_steps(tb, z, K, L):
 # oracle runs: its chain is timed for the CPU baseline and its results are
 # compared with the GPU's; the extended-precision reference for them is
 # stored under tests/golden (rp_ne_fp64_1m_head, 1200 atoms).
-ORACLE_SAMPLE_ATOMS = 600
+ORACLE_SAMPLE_ATOMS = 1000
 
 
 def cpu_model():
