@@ -205,8 +205,11 @@ rpdla_status rpdla_birth_phase(const rpdla_laser* L, int64_t n_slots, const doub
  * reduced to one turn before the float sine / cosine); momentum accumulated
  * in float with Kahan compensation.
  * EINVAL: bad laser, n_slots < 0, slots_per_atom < 1, null pointers with
- * n_slots > 0.  Uses a small stream-ordered device allocation for its work
- * queue (RPDLA_EHIP if that fails).
+ * n_slots > 0.  Uses a small stream-ordered device allocation (1 KiB) for its
+ * work queue (RPDLA_EHIP if that fails): the slots are split into eight
+ * contiguous parts with a counter each, and a wave starts on the part of its
+ * workgroup index mod 8 (the XCD the workgroup is dispatched to), so the
+ * slots of one part pass through one XCD's L2; results do not depend on it.
  * ------------------------------------------------------------------------ */
 rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots,
                         const double* t_birth, const double* x0, const double* y0,
@@ -218,12 +221,12 @@ rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, validation, kernels and results as rpdla_push;
  * it calls no hipMalloc / hipFree and no allocating library routine.  Its
- * work-queue counter lives in a 256-byte library-owned device array (one per
+ * work-queue counters live in a 1 KiB library-owned device array (one per
  * GPU, held until the process ends, its address looked up on the first call
  * on each device), cleared by a fill kernel at the start of every call.
  * Limit: n_slots <= 2^40 (RPDLA_ERANGE beyond).  Every call on one GPU uses
  * that GPU's array, so calls that overlap in time on one GPU (different
- * streams, or several host threads) race on the counter and give wrong
+ * streams, or several host threads) race on the counters and give wrong
  * results: serialize them.  RPDLA_EHIP if the array's address cannot be
  * obtained.
  * ------------------------------------------------------------------------ */

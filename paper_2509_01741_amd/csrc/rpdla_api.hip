@@ -20,10 +20,10 @@
 #include "rpdla_kernels.hpp"
 #include "rpdla_batched.hpp"
 
-// Scratch of the allocation-free push (rpdla_push_noalloc): word 0 is its
-// work-queue counter; the rest pads the array to 256 bytes.  Each GPU holds
-// its own copy until the process ends.
-constexpr int kScratchWords = 32;
+// Scratch of the allocation-free push (rpdla_push_noalloc): its work-queue
+// counters (one per queue part, each on its own 128-byte line), 1 KiB.  Each
+// GPU holds its own copy until the process ends.
+constexpr int kScratchWords = rpdla::kQueueWords;
 static __device__ __align__(256) unsigned long long scratch[kScratchWords];
 
 namespace {
@@ -341,8 +341,8 @@ rpdla_status check_push_args(const rpdla_laser* L, int32_t precision, int64_t n_
     return RPDLA_OK;
 }
 
-// Clear the work counter q (a fill kernel, no memset node) and launch the
-// persistent push that draws slots from it.
+// Clear the work counters q[kQueueWords] (a fill kernel, no memset node) and
+// launch the persistent push that draws slots from them.
 rpdla_status enqueue_push(const rpdla_laser* L, int32_t precision, int64_t n_slots,
                           const double* t_birth, const double* x0, const double* y0,
                           const double* z0, int32_t slots_per_atom, double* ux, double* uy,
@@ -350,7 +350,8 @@ rpdla_status enqueue_push(const rpdla_laser* L, int32_t precision, int64_t n_slo
                           hipStream_t s)
 {
     const DevCfg c = make_cfg(L);
-    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(64), 0, s, q, (int64_t)1);
+    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(rpdla::kQueueWords), 0, s, q,
+                       (int64_t)rpdla::kQueueWords);
     RPDLA_HIP(hipGetLastError());
     rpdla::PushIO io{t_birth, x0, y0, z0, slots_per_atom, n_slots, ux, uy, uz, xf, yf, zf, q};
     switch (L->field) {
@@ -533,7 +534,7 @@ rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots
     if (st != RPDLA_OK || n_slots == 0) return st;
     hipStream_t s = (hipStream_t)stream;
     unsigned long long* q = nullptr;
-    RPDLA_HIP(hipMallocAsync((void**)&q, sizeof(unsigned long long), s));
+    RPDLA_HIP(hipMallocAsync((void**)&q, rpdla::kQueueWords * sizeof(unsigned long long), s));
     st = enqueue_push(L, precision, n_slots, t_birth, x0, y0, z0, slots_per_atom, ux, uy, uz, xf,
                       yf, zf, q, s);
     hipError_t fe = hipFreeAsync(q, s);
@@ -576,8 +577,9 @@ rpdla_status rpdla_push_rr(const rpdla_laser* L, int32_t radiation_reaction, int
     const DevCfg c = make_cfg(L);
     hipStream_t s = (hipStream_t)stream;
     unsigned long long* q = nullptr;
-    RPDLA_HIP(hipMallocAsync((void**)&q, sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(64), 0, s, q, (int64_t)1);
+    RPDLA_HIP(hipMallocAsync((void**)&q, rpdla::kQueueWords * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(rpdla::kQueueWords), 0, s, q,
+                       (int64_t)rpdla::kQueueWords);
     rpdla::PushIO io{t_birth, x0, y0, z0, slots_per_atom, n_slots, ux, uy, uz, xf, yf, zf, q,
                      chi_max};
     const bool rr = radiation_reaction == 1;
@@ -625,8 +627,9 @@ rpdla_status rpdla_push_adaptive(const rpdla_laser* L, const rpdla_adaptive* A, 
     c.ad_max_steps = A->max_steps;
     hipStream_t s = (hipStream_t)stream;
     unsigned long long* q = nullptr;
-    RPDLA_HIP(hipMallocAsync((void**)&q, sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(64), 0, s, q, (int64_t)1);
+    RPDLA_HIP(hipMallocAsync((void**)&q, rpdla::kQueueWords * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(rpdla::zero_u64_kernel, dim3(1), dim3(rpdla::kQueueWords), 0, s, q,
+                       (int64_t)rpdla::kQueueWords);
     rpdla::PushIO io{t_birth, x0, y0, z0, slots_per_atom, n_slots, ux, uy, uz, xf, yf, zf, q};
     io.t_stop = t_stop;
     io.n_acc = (long long*)steps_accepted;

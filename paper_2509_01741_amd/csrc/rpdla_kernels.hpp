@@ -302,6 +302,21 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
     }
 }
 
+// Wave-cooperative refill: lanes with need == true get consecutive queue
+// indices (called by every lane of the wave; -1 for the other lanes).
+__device__ inline int64_t queue_take(unsigned long long* queue, bool need)
+{
+    const uint64_t m = __ballot(need);
+    if (m == 0) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    return need ? (int64_t)(base + (unsigned long long)rank) : -1;
+}
+
 // Lane i ionizes atom order[i] (atom i without an order).  An order that
 // groups atoms of similar work in the same wave keeps the lanes of a wave
 // busy for the same number of panels; the results do not depend on it.
@@ -952,19 +967,42 @@ __device__ inline void elec_extra(const CFG& c, const ElecDP& e, const PushIO& i
     if (io.n_rej) io.n_rej[j] = e.rej;
 }
 
-// Wave-cooperative refill: lanes with need == true get consecutive queue
-// indices (called by every lane of the wave).
-__device__ inline int64_t queue_take(unsigned long long* queue, bool need)
+// The single-configuration push splits its slots into kQueueParts contiguous
+// parts, one counter each (kQueueStride words apart, one 128-byte line per
+// counter).  A wave draws from the part of the XCD it runs on (the hardware
+// XCC_ID register), so the slots of one part are read and written through one
+// XCD's L2, where neighbouring slots share cache lines; lanes that find that
+// part used up go on to the next parts in turn.
+constexpr int kQueueParts = 8;
+constexpr int kQueueStride = 16;
+constexpr int kQueueWords = kQueueParts * kQueueStride;
+
+__device__ inline int xcd_id()
 {
-    const uint64_t m = __ballot(need);
-    if (m == 0) return -1;
-    const int lane = __lane_id();
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(m));
-    base = __shfl(base, leader);
-    const int rank = __popcll(m & ((1ull << lane) - 1ull));
-    return need ? (int64_t)(base + (unsigned long long)rank) : -1;
+    // hwreg(HW_REG_XCC_ID, 0, 4): id 20, offset 0, size 4
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kQueueParts - 1);
+}
+
+// Wave-cooperative refill from the parts of [0, n): lanes with need == true
+// get an index, or -1 when every part is used up (a part's counter only
+// grows, so a part once used up stays so).
+__device__ inline int64_t queue_take_xcd(unsigned long long* queue, int64_t n, bool need)
+{
+    const int home = xcd_id();
+    int64_t got = -1;
+    bool want = need;
+#pragma unroll 1
+    for (int m = 0; m < kQueueParts; ++m) {
+        if (__ballot(want) == 0) break;
+        const int part = (home + m) & (kQueueParts - 1);
+        const int64_t j = queue_take(queue + part * kQueueStride, want);
+        const int64_t lo = (n * part) >> 3, hi = (n * (part + 1)) >> 3;   // n / 8 parts
+        if (want && j >= 0 && lo + j < hi) {
+            got = lo + j;
+            want = false;
+        }
+    }
+    return got;
 }
 
 // Waves per SIMD each electron form is compiled for (its register budget):
@@ -987,27 +1025,24 @@ __global__ void __launch_bounds__(256, ElecWaves<ELEC>::value) push_kernel(DevCf
         while (true) {
             const bool need = (idx < 0) && !exhausted;
             if (__ballot(need) == 0) break;
-            const int64_t j = queue_take(io.queue, need);
-            if (need) {
-                if (j >= io.n_slots) {
-                    exhausted = true;
+            const int64_t j = queue_take_xcd(io.queue, io.n_slots, need);
+            if (need && j < 0) exhausted = true;
+            if (need && j >= 0) {
+                const double t0 = io.tb[j];
+                if (!(t0 < __builtin_inf())) {
+                    write_nan<HasExtra<ELEC>::value>(io, j);
                 } else {
-                    const double t0 = io.tb[j];
-                    if (!(t0 < __builtin_inf())) {
+                    const int64_t a = j / io.spa;
+                    if (!elec_init(c, e, t0, io.x0[a], io.y0[a], io.z0[a])) {
                         write_nan<HasExtra<ELEC>::value>(io, j);
-                    } else {
-                        const int64_t a = j / io.spa;
-                        if (!elec_init(c, e, t0, io.x0[a], io.y0[a], io.z0[a])) {
-                            write_nan<HasExtra<ELEC>::value>(io, j);
-                            continue;
-                        }
-                        idx = j;
-                        if (e.N <= 0) {
-                            elec_final(c, e, io.ux[j], io.uy[j], io.uz[j], io.xf[j], io.yf[j],
-                                       io.zf[j]);
-                            elec_extra(c, e, io, j);
-                            idx = -1;
-                        }
+                        continue;
+                    }
+                    idx = j;
+                    if (e.N <= 0) {
+                        elec_final(c, e, io.ux[j], io.uy[j], io.uz[j], io.xf[j], io.yf[j],
+                                   io.zf[j]);
+                        elec_extra(c, e, io, j);
+                        idx = -1;
                     }
                 }
             }
