@@ -385,3 +385,26 @@ def test_invalid_arguments(env):
         B.rpdla_histogram(x, x, x, x, B.rpdla_hist_spec(4, 4, 1.0, 1.0, 0))
     with pytest.raises(TypeError):
         B.rpdla_ionize(L, 0, 0, 0, x.float(), x, x, 1, 2)
+
+
+@pytest.mark.parametrize("order", [5, 25])
+def test_ionize_work_order_bitwise(env, order):
+    """From 16,384 atoms on, rpdla_ionize hands the atoms to the lanes in the
+    order of their work key (a radix sort), so that a wave holds atoms of
+    alike windows.  Each atom's arithmetic is the same either way, so the
+    birth times equal, bit for bit, those of calls below that size, which
+    take the atoms in index order (the same atoms, addressed by
+    first_atom)."""
+    torch, B, O = env
+    L, _ = _lasers(B, O, order)
+    n, parts, seed, cfg = 20000, (0, 7000, 14000, 20000), 21, 4
+    x, y, z = B.rpdla_sample_atoms(seed, cfg, 0, n, 2 * BEAM["w0"], B.rpdla_rayleigh(L))
+    print(f"ionize in work order: field {order}, {n} atoms, states 1-10", flush=True)
+    tb = B.rpdla_ionize(L, seed, cfg, 0, x, y, z, 1, 10).cpu().numpy()
+    ref = np.concatenate([
+        B.rpdla_ionize(L, seed, cfg, a, x[a:b].contiguous(), y[a:b].contiguous(),
+                       z[a:b].contiguous(), 1, 10).cpu().numpy() for a, b in zip(parts, parts[1:])])
+    torch.cuda.synchronize()
+    born = np.isfinite(tb)
+    assert 0 < born.sum() < tb.size
+    assert np.array_equal(tb.view(np.uint64), ref.view(np.uint64))
