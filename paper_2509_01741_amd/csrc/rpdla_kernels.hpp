@@ -219,7 +219,7 @@ __device__ double solve_crossing(const CFG& c, const AdkState& st, const AtomGeo
 // level (adk_a2thr) at every node.
 template <class CFG>
 __device__ inline bool state_window(const CFG& c, const AdkState& st, double bound2, double Zc,
-                                    double tau_s, double h, int64_t M, int64_t& j_lo, int64_t& j_hi)
+                                    double tau_s, double h, int32_t M, int32_t& j_lo, int32_t& j_hi)
 {
     const double thr = st.a2thr;
     if (!(bound2 >= thr)) return false;            // never reaches a nonzero rate
@@ -228,8 +228,47 @@ __device__ inline bool state_window(const CFG& c, const AdkState& st, double bou
     const double half = smax / c.inv_T0n;          // in normalized time
     const double lo = floor((Zc - half - tau_s) / h) - 1.0;
     const double hi = ceil((Zc + half - tau_s) / h) + 1.0;
-    j_lo = lo < 0.0 ? 0 : (lo > (double)(M - 1) ? M - 1 : (int64_t)lo);
-    j_hi = hi > (double)(M - 1) ? M - 1 : (hi < 0.0 ? 0 : (int64_t)hi);
+    j_lo = lo < 0.0 ? 0 : (lo > (double)(M - 1) ? M - 1 : (int32_t)lo);
+    j_hi = hi > (double)(M - 1) ? M - 1 : (hi < 0.0 ? 0 : (int32_t)hi);
+    return true;
+}
+
+// Upper bound of what the panel loop below can add up for state st over the
+// panels j0..j1 (the first one from d_from): a panel's GL-4 estimate is at
+// most its width times the largest rate at its nodes, and the rate is at
+// most the ADK rate at the largest |a|^2 the field bound allows there,
+// |a|^2 <= b2 exp(-2 s^2) (lb2 = ln b2), capped at the |a|^2 where the rate
+// itself peaks.  Panels go in groups of kBoundGroup (one optical period);
+// each group is charged its width times that rate at its smallest |s|.  When
+// twice this bound stays below the state's threshold the loop could not reach
+// it: the state, and so every later one, is never born, which is what
+// integrating all the panels would give.  never_reaches() answers that,
+// stopping as soon as the bound passes half the threshold.
+constexpr int32_t kBoundGroup = 200;
+
+template <class CFG>
+__device__ inline bool never_reaches(const CFG& c, const AdkState& st, double lb2, double d_s,
+                                     double d_e, double h, int32_t M, int32_t j0, int32_t j1,
+                                     double d_from, double target)
+{
+    // ln |a|^2 where ln w = c0 - c1h ln|a|^2 - c2 |a|^-1 peaks
+    const double la2pk = (st.c1h > 0.0) ? 2.0 * log(st.c2 / (2.0 * st.c1h)) : __builtin_inf();
+    const int32_t groups = (j1 - j0) / kBoundGroup + 1;
+    double sum = 0.0, da = d_from;
+#pragma unroll 1
+    for (int32_t g = 1; g <= groups; ++g) {
+        // the group ends where panel j0 + g kBoundGroup starts (the last one at
+        // the end of panel j1), as the panel loop forms its panel edges
+        const int32_t je = j0 + g * kBoundGroup;
+        const double db = (g < groups) ? d_s + (double)je * h
+                                       : ((j1 == M - 1) ? d_e : d_s + (double)(j1 + 1) * h);
+        const double smin = (da <= 0.0 && db >= 0.0) ? 0.0 : fmin(fabs(da), fabs(db)) * c.inv_T0n;
+        const double la2 = fmin(lb2 - 2.0 * smin * smin, la2pk);
+        const double lw = st.c0 - st.c1h * la2 - st.c2 * fm::exp_f64(-0.5 * la2);
+        sum += (db - da) * fm::exp_f64(lw);
+        if (!(2.0 * sum < target)) return false;
+        da = db;
+    }
     return true;
 }
 
@@ -247,10 +286,10 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
     const double dz = (c.window == 0) ? 0.0 : -Z;   // window start relative to arrival
     const double d_s = dz - c.tb_n, d_e = dz + c.ta_n;
     const double h = c.hn;
-    const int64_t M = (int64_t)ceil((d_e - d_s) / h);
+    // panels in the window (below 2^31: the host limits window / dt to 2e9)
+    const int32_t M = (int32_t)ceil((d_e - d_s) / h);
     const double b2 = bound2_f64<FIELD>(c, X, Y, Z);
     const double Zc = 0.0;  // the envelope peaks at d = 0 for the pulse models
-    const AtomGeom ag = atom_geom<FIELD>(c, X, Y, Z);
 
     int s = 0;
     double target = -log(uniform_j(seed, cfg, atom, k_first + 2));
@@ -262,11 +301,16 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
     }
     if (s >= K) return;
     AdkState st = adk_state(c, k_first - 1 + s);
-    int64_t j_lo, j_hi;
+    int32_t j_lo, j_hi;
     if (!state_window(c, st, b2, Zc, d_s, h, M, j_lo, j_hi)) return;
+    // the envelope bound holds for the pulse models (not the static field)
+    if (FIELD != 11 &&
+        never_reaches(c, st, log(b2), d_s, d_e, h, M, j_lo, j_hi, d_s + (double)j_lo * h, target))
+        return;
+    const AtomGeom ag = atom_geom<FIELD>(c, X, Y, Z);
     double I = 0.0;
     double tstart = d_s;
-    for (int64_t j = j_lo; j < M; ++j) {
+    for (int32_t j = j_lo; j < M; ++j) {
         if (j > j_hi) break;
         const double a = d_s + (double)j * h;
         const double b = (j == M - 1) ? d_e : d_s + (double)(j + 1) * h;
@@ -283,13 +327,21 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
             I = 0.0;
             tstart = t;
             st = adk_state(c, k_first - 1 + s);
-            int64_t nlo, nhi;
+            int32_t nlo, nhi;
             if (!state_window(c, st, b2, Zc, d_s, h, M, nlo, nhi)) {
                 if (!(target > 0.0)) { j_hi = M - 1; continue; }
                 done = true;
                 break;
             }
             j_hi = (target > 0.0) ? nhi : M - 1;
+            if (FIELD != 11 && target > 0.0) {
+                const int32_t j0 = nlo > j ? nlo : j;
+                const double d0 = nlo > j ? d_s + (double)nlo * h : t;
+                if (never_reaches(c, st, log(b2), d_s, d_e, h, M, j0, j_hi, d0, target)) {
+                    done = true;
+                    break;
+                }
+            }
             if (target > 0.0 && nlo > j) {
                 // before its window the new state's ln w stays below the
                 // skip level at every node, the same bound that starts the
