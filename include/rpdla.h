@@ -207,9 +207,10 @@ rpdla_status rpdla_birth_phase(const rpdla_laser* L, int64_t n_slots, const doub
  * EINVAL: bad laser, n_slots < 0, slots_per_atom < 1, null pointers with
  * n_slots > 0.  Uses a small stream-ordered device allocation (1 KiB) for its
  * work queue (RPDLA_EHIP if that fails): the slots are split into eight
- * contiguous parts with a counter each, and a wave starts on the part of its
- * workgroup index mod 8 (the XCD the workgroup is dispatched to), so the
- * slots of one part pass through one XCD's L2; results do not depend on it.
+ * contiguous parts with a counter each, and a wave draws from the part of the
+ * XCD it runs on (the hardware XCC_ID register) before it moves on to the
+ * others, so the slots of one part pass through one XCD's L2; results do not
+ * depend on it.
  * ------------------------------------------------------------------------ */
 rpdla_status rpdla_push(const rpdla_laser* L, int32_t precision, int64_t n_slots,
                         const double* t_birth, const double* x0, const double* y0,

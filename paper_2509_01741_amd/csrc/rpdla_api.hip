@@ -24,6 +24,7 @@
 // counters (one per queue part, each on its own 128-byte line), 1 KiB.  Each
 // GPU holds its own copy until the process ends.
 constexpr int kScratchWords = rpdla::kQueueWords;
+static_assert(rpdla::kQueueParts == 8, "queue_take_xcd splits the slots with a shift by 3");
 static __device__ __align__(256) unsigned long long scratch[kScratchWords];
 
 namespace {
