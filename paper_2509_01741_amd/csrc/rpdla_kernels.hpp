@@ -242,9 +242,33 @@ __device__ inline bool state_window(const CFG& c, const AdkState& st, double bou
 // each group is charged its width times that rate at its smallest |s|.  When
 // twice this bound stays below the state's threshold the loop could not reach
 // it: the state, and so every later one, is never born, which is what
-// integrating all the panels would give.  never_reaches() answers that,
-// stopping as soon as the bound passes half the threshold.
+// integrating all the panels would give.  never_reaches() answers that.  It
+// takes the group nearest the envelope peak (s = 0) first, the largest term,
+// and stops as soon as the sum passes half the threshold, so a state that
+// will be born costs one or two groups.
 constexpr int32_t kBoundGroup = 200;
+
+// Edges of group g (0-based) of panels j0..j1, as the panel loop forms its
+// panel edges: from d_from or panel j0 + g kBoundGroup to the start of the
+// next group or the end of panel j1.
+__device__ inline void bound_group(int32_t g, int32_t groups, int32_t j0, int32_t j1, int32_t M,
+                                   double d_s, double d_e, double h, double d_from, double& da,
+                                   double& db)
+{
+    da = (g == 0) ? d_from : d_s + (double)(j0 + g * kBoundGroup) * h;
+    db = (g + 1 < groups) ? d_s + (double)(j0 + (g + 1) * kBoundGroup) * h
+                          : ((j1 == M - 1) ? d_e : d_s + (double)(j1 + 1) * h);
+}
+
+template <class CFG>
+__device__ inline double bound_group_rate(const CFG& c, const AdkState& st, double lb2, double la2pk,
+                                          double da, double db)
+{
+    const double smin = (da <= 0.0 && db >= 0.0) ? 0.0 : fmin(fabs(da), fabs(db)) * c.inv_T0n;
+    const double la2 = fmin(lb2 - 2.0 * smin * smin, la2pk);
+    const double lw = st.c0 - st.c1h * la2 - st.c2 * fm::exp_f64(-0.5 * la2);
+    return (db - da) * fm::exp_f64(lw);
+}
 
 template <class CFG>
 __device__ inline bool never_reaches(const CFG& c, const AdkState& st, double lb2, double d_s,
@@ -254,20 +278,21 @@ __device__ inline bool never_reaches(const CFG& c, const AdkState& st, double lb
     // ln |a|^2 where ln w = c0 - c1h ln|a|^2 - c2 |a|^-1 peaks
     const double la2pk = (st.c1h > 0.0) ? 2.0 * log(st.c2 / (2.0 * st.c1h)) : __builtin_inf();
     const int32_t groups = (j1 - j0) / kBoundGroup + 1;
-    double sum = 0.0, da = d_from;
+    // the group holding d = 0, or the one nearest to it
+    const double jpk = floor(-d_s / h) - (double)j0;
+    const int32_t gpk = jpk <= 0.0 ? 0
+                      : (jpk >= (double)(groups - 1) * kBoundGroup ? groups - 1
+                                                                   : (int32_t)jpk / kBoundGroup);
+    double da, db;
+    bound_group(gpk, groups, j0, j1, M, d_s, d_e, h, d_from, da, db);
+    double sum = bound_group_rate(c, st, lb2, la2pk, da, db);
+    if (!(2.0 * sum < target)) return false;
 #pragma unroll 1
-    for (int32_t g = 1; g <= groups; ++g) {
-        // the group ends where panel j0 + g kBoundGroup starts (the last one at
-        // the end of panel j1), as the panel loop forms its panel edges
-        const int32_t je = j0 + g * kBoundGroup;
-        const double db = (g < groups) ? d_s + (double)je * h
-                                       : ((j1 == M - 1) ? d_e : d_s + (double)(j1 + 1) * h);
-        const double smin = (da <= 0.0 && db >= 0.0) ? 0.0 : fmin(fabs(da), fabs(db)) * c.inv_T0n;
-        const double la2 = fmin(lb2 - 2.0 * smin * smin, la2pk);
-        const double lw = st.c0 - st.c1h * la2 - st.c2 * fm::exp_f64(-0.5 * la2);
-        sum += (db - da) * fm::exp_f64(lw);
+    for (int32_t g = 0; g < groups; ++g) {
+        if (g == gpk) continue;
+        bound_group(g, groups, j0, j1, M, d_s, d_e, h, d_from, da, db);
+        sum += bound_group_rate(c, st, lb2, la2pk, da, db);
         if (!(2.0 * sum < target)) return false;
-        da = db;
     }
     return true;
 }
