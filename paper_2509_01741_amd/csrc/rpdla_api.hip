@@ -258,7 +258,7 @@ rpdla_status launch_ionize(const DevCfg& c, uint64_t seed, uint32_t cfg, uint64_
     uint32_t* idx_out = (uint32_t*)(buf + 3 * arr);
     rpdla_status r = RPDLA_OK;
     hipLaunchKernelGGL(rpdla::ionize_key_kernel<FIELD>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0,
-                       st, c, n, x, y, z, key_in, idx_in);
+                       st, c, seed, cfg, first, n, x, y, z, kf, kl, key_in, idx_in);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = hipcub::DeviceRadixSort::SortPairs(buf + 4 * arr, sort_bytes, key_in, key_out, idx_in,

@@ -411,21 +411,45 @@ __global__ void __launch_bounds__(256, 3) ionize_kernel(
                        z[a] * c.k, k_first, K, t_birth + a * K);
 }
 
-// Work key of each atom for that order: the bound of its peak |a|^2 (the
+// Work key of each atom for that order: first the number of its states that
+// the rate bound (never_reaches) does not rule out from the window start --
+// those the panel loop may integrate; the thresholds are random, so atoms of
+// one field strength differ in it -- then the bound of its peak |a|^2 (the
 // states' windows, and so the panels an atom integrates, grow with it), as
-// the bit pattern of a non-negative float, which orders like the value.
+// the top bits of a non-negative float, which order like the value.
 template <int FIELD>
-__global__ void __launch_bounds__(256) ionize_key_kernel(DevCfg c, int64_t n,
+__global__ void __launch_bounds__(256) ionize_key_kernel(DevCfg c, uint64_t seed, uint32_t cfg,
+                                                         uint64_t first_atom, int64_t n,
                                                          const double* __restrict__ x,
                                                          const double* __restrict__ y,
-                                                         const double* __restrict__ z,
-                                                         uint32_t* __restrict__ key,
+                                                         const double* __restrict__ z, int k_first,
+                                                         int k_last, uint32_t* __restrict__ key,
                                                          uint32_t* __restrict__ idx)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float b2 = (float)bound2_f64<FIELD>(c, x[i] * c.k, y[i] * c.k, z[i] * c.k);
-    key[i] = __float_as_uint(b2 > 0.0f ? b2 : 0.0f);
+    const double X = x[i] * c.k, Y = y[i] * c.k, Z = z[i] * c.k;
+    const double b2 = bound2_f64<FIELD>(c, X, Y, Z);
+    uint32_t open = 0;
+    if (FIELD != 11) {
+        const double dz = (c.window == 0) ? 0.0 : -Z;
+        const double d_s = dz - c.tb_n, d_e = dz + c.ta_n;
+        const double h = c.hn;
+        const int32_t M = (int32_t)ceil((d_e - d_s) / h);
+        const double lb2 = log(b2);
+        for (int k = k_first; k <= k_last; ++k) {
+            const double target = -log(uniform_j(seed, cfg, first_atom + (uint64_t)i, k + 2));
+            if (!(target > 0.0)) { ++open; continue; }
+            const AdkState st = adk_state(c, k - 1);
+            int32_t j_lo, j_hi;
+            if (!state_window(c, st, b2, 0.0, d_s, h, M, j_lo, j_hi)) break;
+            if (never_reaches(c, st, lb2, d_s, d_e, h, M, j_lo, j_hi, d_s + (double)j_lo * h, target))
+                break;
+            ++open;
+        }
+    }
+    const float b2f = (float)b2;
+    key[i] = (open << 27) | (__float_as_uint(b2f > 0.0f ? b2f : 0.0f) >> 4);
     idx[i] = (uint32_t)i;
 }
 
