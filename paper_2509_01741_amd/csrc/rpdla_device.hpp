@@ -443,8 +443,10 @@ __device__ inline double bound2_f64(const CFG& c, double X, double Y, double Z)
 // model without printing a formula): l = m = 0, l* = n* - 1, in log space,
 // per unit normalized time.  w = 0 when |a| = 0 or ln w < lnw_zero.
 // ---------------------------------------------------------------------------
-// Rate constants of one charge state, picked out of the configuration record
-// with static indices (no dynamic indexing into the record).
+// Rate constants of one charge state, read from the configuration record at
+// the state's index (from the kernel-argument segment in the single-
+// configuration kernels, from LDS in the batched ones; picking them with
+// static indices held all forty in scalar registers, which spilled).
 struct AdkState {
     double c0, c1h, c2, a2thr, lnw_zero;
 };
@@ -452,14 +454,7 @@ struct AdkState {
 template <class CFG>
 __device__ inline AdkState adk_state(const CFG& c, int s)
 {
-    AdkState a{c.adk_c0[0], c.adk_c1h[0], c.adk_c2[0], c.adk_a2thr[0], c.lnw_zero};
-#pragma unroll
-    for (int i = 1; i < kMaxStates; ++i) {
-        if (s == i) {
-            a.c0 = c.adk_c0[i]; a.c1h = c.adk_c1h[i]; a.c2 = c.adk_c2[i]; a.a2thr = c.adk_a2thr[i];
-        }
-    }
-    return a;
+    return AdkState{c.adk_c0[s], c.adk_c1h[s], c.adk_c2[s], c.adk_a2thr[s], c.lnw_zero};
 }
 
 __device__ inline double adk_rate_n(const AdkState& st, double a2)
@@ -467,7 +462,7 @@ __device__ inline double adk_rate_n(const AdkState& st, double a2)
     if (!(a2 > 0.0)) return 0.0;
     const double l = st.c0 - st.c1h * log(a2) - st.c2 * rsqrt(a2);
     if (l < st.lnw_zero) return 0.0;
-    return fm::exp_f64(l);
+    return fm::exp_fin_f64(l);   // l >= lnw_zero > -745: no range guard needed
 }
 
 }  // namespace rpdla

@@ -155,7 +155,7 @@ __device__ inline double emag2_atom(const CFG& c, const AtomGeom& a, double d)
 {
     if constexpr (FIELD == 1 || FIELD == 3 || FIELD == 5) {
         const double s = d * c.inv_T0n;
-        const double g = c.a0 * fm::exp_f64(a.mrD - s * s);
+        const double g = c.a0 * fm::exp_fin_f64(a.mrD - s * s);
         // the sign (-1)^n of the half-angle form cancels in the squares
         double sg, kp;
         fm::cis_half2_f64(d, a.psi_c, &sg, &kp);
