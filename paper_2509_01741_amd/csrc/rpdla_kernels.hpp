@@ -276,7 +276,8 @@ __device__ inline bool never_reaches(const CFG& c, const AdkState& st, double lb
                                      double d_from, double target)
 {
     // ln |a|^2 where ln w = c0 - c1h ln|a|^2 - c2 |a|^-1 peaks
-    const double la2pk = (st.c1h > 0.0) ? 2.0 * log(st.c2 / (2.0 * st.c1h)) : __builtin_inf();
+    const double la2pk = (st.c1h > 0.0) ? 2.0 * fm::log_pos_f64(st.c2 / (2.0 * st.c1h))
+                                         : __builtin_inf();
     const int32_t groups = (j1 - j0) / kBoundGroup + 1;
     // the group holding d = 0, or the one nearest to it
     const double jpk = floor(-d_s / h) - (double)j0;
@@ -330,7 +331,7 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
     if (!state_window(c, st, b2, Zc, d_s, h, M, j_lo, j_hi)) return;
     // the envelope bound holds for the pulse models (not the static field)
     if (FIELD != 11 &&
-        never_reaches(c, st, log(b2), d_s, d_e, h, M, j_lo, j_hi, d_s + (double)j_lo * h, target))
+        never_reaches(c, st, fm::log_pos_f64(b2), d_s, d_e, h, M, j_lo, j_hi, d_s + (double)j_lo * h, target))
         return;
     const AtomGeom ag = atom_geom<FIELD>(c, X, Y, Z);
     double I = 0.0;
@@ -362,7 +363,7 @@ __device__ void ionize_atom(const CFG& c, uint64_t seed, uint32_t cfg, uint64_t 
             if (FIELD != 11 && target > 0.0) {
                 const int32_t j0 = nlo > j ? nlo : j;
                 const double d0 = nlo > j ? d_s + (double)nlo * h : t;
-                if (never_reaches(c, st, log(b2), d_s, d_e, h, M, j0, j_hi, d0, target)) {
+                if (never_reaches(c, st, fm::log_pos_f64(b2), d_s, d_e, h, M, j0, j_hi, d0, target)) {
                     done = true;
                     break;
                 }
@@ -436,7 +437,7 @@ __global__ void __launch_bounds__(256) ionize_key_kernel(DevCfg c, uint64_t seed
         const double d_s = dz - c.tb_n, d_e = dz + c.ta_n;
         const double h = c.hn;
         const int32_t M = (int32_t)ceil((d_e - d_s) / h);
-        const double lb2 = log(b2);
+        const double lb2 = fm::log_pos_f64(b2);
         for (int k = k_first; k <= k_last; ++k) {
             const double target = -log(uniform_j(seed, cfg, first_atom + (uint64_t)i, k + 2));
             if (!(target > 0.0)) { ++open; continue; }
