@@ -459,8 +459,10 @@ __device__ inline AdkState adk_state(const CFG& c, int s)
 
 __device__ inline double adk_rate_n(const AdkState& st, double a2)
 {
-    if (!(a2 > 0.0)) return 0.0;
-    const double l = st.c0 - st.c1h * fm::log_pos_f64(a2) - st.c2 * rsqrt(a2);
+    // below 2^-960 the c2/|a| term alone puts ln w under any lnw_zero (c2 > 1e-30
+    // for every state), so the rate is zero there either way
+    if (!(a2 >= 0x1.0p-960)) return 0.0;
+    const double l = st.c0 - st.c1h * fm::log_pos_f64(a2) - st.c2 * fm::rsqrt_mid_f64(a2);
     if (l < st.lnw_zero) return 0.0;
     return fm::exp_fin_f64(l);   // l >= lnw_zero > -745: no range guard needed
 }
