@@ -163,10 +163,14 @@ rpdla_status rpdla_sample_atoms_annulus(uint64_t seed, uint32_t cfg_id, uint64_t
  * potentials, w = 0 where ln w[1/s] < -700.
  * t_birth: device double[n_atoms * K], K = k_last - k_first + 1, atom-major
  * (slot j*K + (k - k_first)), seconds, +INF where the state is not reached
- * in the window.  From 16384 atoms on, the atoms are taken in an order that
- * groups similar work in each wave (a sort by their peak-field bound), which
- * needs stream-ordered scratch of about 16 bytes per atom (hipMallocAsync /
- * hipFreeAsync on `stream`); results do not depend on the order.  EINVAL: bad
+ * in the window.  A state whose rate, bounded through the field's envelope,
+ * cannot reach its threshold within the window is left unborn without
+ * integrating its panels (the same result).  From 16384 atoms on, the atoms
+ * are taken in an order that groups similar work in each wave (a sort by the
+ * number of states that bound leaves open, then by the peak-field bound),
+ * which needs stream-ordered scratch of about 16 bytes per atom
+ * (hipMallocAsync / hipFreeAsync on `stream`); results do not depend on the
+ * order.  EINVAL: bad
  * laser, 1 <= k_first <= k_last <= 10 violated, null pointers with
  * n_atoms > 0.
  * ------------------------------------------------------------------------ */
