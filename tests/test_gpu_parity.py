@@ -408,3 +408,26 @@ def test_ionize_work_order_bitwise(env, order):
     born = np.isfinite(tb)
     assert 0 < born.sum() < tb.size
     assert np.array_equal(tb.view(np.uint64), ref.view(np.uint64))
+
+
+def test_push_queue_parts_small_and_ragged(env):
+    """The push draws slots from eight contiguous parts of the slot range (one
+    per XCD) and moves on to the other parts when its own runs dry.  For slot
+    counts below, at and around multiples of eight (several parts empty), every
+    slot is pushed exactly once: outputs prefilled with a marker all change,
+    and equal, bit for bit, the same slots of one launch over all of them."""
+    torch, B, O = env
+    L, _ = _lasers(B, O, 5)
+    n_atoms, K = 130, 8
+    x, y, z = B.rpdla_sample_atoms(3, 9, 0, n_atoms, 2 * BEAM["w0"], B.rpdla_rayleigh(L))
+    tb = B.rpdla_ionize(L, 3, 9, 0, x, y, z, 1, K)
+    full = [o.cpu().numpy() for o in B.rpdla_push(L, B.RPDLA_FP64, tb, x, y, z, K)]
+    for n in (1, 2, 7, 8, 9, 15, 16, 17, 63, 65, 1000, n_atoms * K):
+        print(f"push queue parts: {n} slots", flush=True)
+        out = tuple(torch.full((n,), 12345.0, dtype=torch.float64, device="cuda") for _ in range(6))
+        B.rpdla_push(L, B.RPDLA_FP64, tb[:n].contiguous(), x, y, z, K, out=out)
+        torch.cuda.synchronize()
+        for o, f in zip(out, full):
+            a = o.cpu().numpy()
+            assert not np.any(a == 12345.0), n
+            assert np.array_equal(a.view(np.uint64), f[:n].view(np.uint64)), n
